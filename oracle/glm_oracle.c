@@ -1,0 +1,247 @@
+/*
+ * FP64 CPU oracle for the Bayesian logistic-regression log-posterior and its
+ * gradient.  TEST INFRASTRUCTURE ONLY: it exists so that tests, the smoke
+ * check and the CPU-baseline leg of the benchmark can check the GPU library
+ * against a plain, slow, obviously correct computation.  Nothing in the
+ * product links or calls it, and it shares no code with the GPU library.
+ *
+ * What it computes (plain definition, written out):
+ *   u_n   = sum_k x_nk beta_k                                  (linear predictor)
+ *   L     = sum_n [ y_n u_n - softplus(u_n) ]
+ *           which is the paper's logistic log-likelihood (Sec. 3.1.1,
+ *           eq-loglike-binlogit): -( (1-y) u + log(1+exp(-u)) ) = y u - softplus(u)
+ *   g_L   = sum_n (y_n - sigmoid(u_n)) x_n = X^t g_f          (Sec. 4.2,
+ *           eq-grad-expanded / eq-grad-compact, with f_n'(u) = y_n - 1/(1+e^-u))
+ *   prior : Gaussian N(m, prec^-1 I) on beta (Sec. 3.1.1 names a Gaussian prior
+ *           without fixing it); its log density up to the normalising constant
+ *           is -prec/2 |beta - m|^2 with gradient -prec (beta - m).
+ *   f     = L - prec/2 |beta - m|^2,   g = g_L - prec (beta - m).
+ *
+ * The response y_n must be 0 or 1.  softplus and sigmoid are evaluated in the
+ * overflow-free forms softplus(u) = max(u,0) + log1p(exp(-|u|)) and
+ * sigmoid(u) = 1/(1+exp(-u)) (u >= 0) or exp(u)/(1+exp(u)) (u < 0); in exact
+ * arithmetic these equal log(1+exp(u)) and 1/(1+exp(-u)).
+ *
+ * Precision: all arithmetic in IEEE double.  The sums over rows n are taken
+ * in ascending n with Neumaier's compensated summation (A. Neumaier, ZAMM 54,
+ * 1974), one running sum for f and one for each g_k.  The stored X is
+ * converted to double element by element (exact for FP32 and BF16; for FP8
+ * the decoded code times its FP32 column scale, also exact in double).
+ *
+ * Storage formats (decoders / encoders follow the bit-level definitions):
+ *   BF16: the upper 16 bits of an IEEE binary32; encoding rounds to nearest,
+ *         ties to even.
+ *   FP8 E4M3 (OCP "E4M3FN"): 1 sign, 4 exponent (bias 7), 3 mantissa bits,
+ *         no infinities, S.1111.111 is NaN, largest finite 448; encoding of
+ *         x / s_k rounds to nearest even and saturates at +-448.  The column
+ *         scale is s_k = max_n |x_nk| / 448 in FP32 (s_k = 1 for an all-zero
+ *         column).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_F64 = 0, ORC_F32 = 1, ORC_BF16 = 2, ORC_FP8 = 3 };
+
+/* ---------------------------------------------------------------- decoding */
+
+double orc_bf16_to_double(uint16_t h) {
+    uint32_t bits = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &bits, 4);
+    return (double)f;
+}
+
+double orc_fp8_to_double(uint8_t q) {
+    int sign = (q >> 7) & 1;
+    int e = (q >> 3) & 0xF;
+    int m = q & 7;
+    double v;
+    if (e == 0xF && m == 7) return NAN;
+    if (e == 0)
+        v = ldexp((double)m, -9);               /* subnormal: m * 2^-6 / 8 */
+    else
+        v = ldexp(1.0 + m / 8.0, e - 7);
+    return sign ? -v : v;
+}
+
+static double elem(const void* X, int dtype, int64_t idx, const float* scale, int k) {
+    switch (dtype) {
+    case ORC_F64: return ((const double*)X)[idx];
+    case ORC_F32: return (double)((const float*)X)[idx];
+    case ORC_BF16: return orc_bf16_to_double(((const uint16_t*)X)[idx]);
+    case ORC_FP8: return orc_fp8_to_double(((const uint8_t*)X)[idx]) * (double)scale[k];
+    }
+    return NAN;
+}
+
+/* ------------------------------------------------------- compensated sums */
+
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum* a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else                       a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double nsum_get(const nsum* a) { return a->s + a->c; }
+
+/* ------------------------------------------------------- scalar functions */
+
+double orc_softplus(double u) {
+    return (u > 0.0 ? u : 0.0) + log1p(exp(-fabs(u)));
+}
+
+double orc_sigmoid(double u) {
+    if (u >= 0.0) return 1.0 / (1.0 + exp(-u));
+    double e = exp(u);
+    return e / (1.0 + e);
+}
+
+/* ---------------------------------------------------------------- the oracle
+
+ * X: row-major, element (n, k) at X[n * ldx + k] in the storage dtype.
+ * scale: K FP32 column scales (FP8 only; ignored otherwise).
+ * y: N bytes, each 0 or 1.  beta: K doubles.  mean: K doubles or NULL (zero).
+ * out: 1 + K doubles, out[0] = f, out[1 + k] = g_k.
+ * Returns 0, or -1 on invalid arguments (K < 1, N < 0, ldx < K, y not 0/1,
+ * NULL pointers where data is needed, unknown dtype).
+ */
+int orc_logpost_grad(const void* X, int dtype, int64_t ldx, const float* scale,
+                     const uint8_t* y, int64_t N, int K, const double* beta,
+                     double prec, const double* mean, double* out) {
+    if (K < 1 || N < 0 || ldx < K || !beta || !out) return -1;
+    if (dtype < ORC_F64 || dtype > ORC_FP8) return -1;
+    if (N > 0 && (!X || !y)) return -1;
+    if (dtype == ORC_FP8 && N > 0 && !scale) return -1;
+
+    nsum f = {0.0, 0.0};
+    nsum* g = (nsum*)calloc((size_t)K, sizeof(nsum));
+    double* x = (double*)malloc((size_t)K * sizeof(double));
+    if (!g || !x) { free(g); free(x); return -1; }
+
+    for (int64_t n = 0; n < N; ++n) {
+        if (y[n] > 1) { free(g); free(x); return -1; }
+        double yn = (double)y[n];
+        double u = 0.0;
+        for (int k = 0; k < K; ++k) {
+            x[k] = elem(X, dtype, n * ldx + k, scale, k);
+            u += x[k] * beta[k];
+        }
+        nsum_add(&f, yn * u - orc_softplus(u));
+        double r = yn - orc_sigmoid(u);
+        for (int k = 0; k < K; ++k) nsum_add(&g[k], r * x[k]);
+    }
+
+    double pf = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double d = beta[k] - (mean ? mean[k] : 0.0);
+        pf += d * d;
+        out[1 + k] = nsum_get(&g[k]) - prec * d;
+    }
+    out[0] = nsum_get(&f) - 0.5 * prec * pf;
+    free(g);
+    free(x);
+    return 0;
+}
+
+/* Several evaluation points on one data set: betas and out are b x K and
+ * b x (1 + K), row-major; means is b x K or NULL. */
+int orc_logpost_grad_multi(const void* X, int dtype, int64_t ldx, const float* scale,
+                           const uint8_t* y, int64_t N, int K, const double* betas,
+                           int b, double prec, const double* means, double* out) {
+    for (int i = 0; i < b; ++i) {
+        int rc = orc_logpost_grad(X, dtype, ldx, scale, y, N, K, betas + (int64_t)i * K,
+                                  prec, means ? means + (int64_t)i * K : NULL,
+                                  out + (int64_t)i * (1 + K));
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* Hierarchical model (Sec. 4.1): group g owns rows offsets[g] .. offsets[g+1]-1
+ * of the stacked X and y and its own coefficient vector betas[g*K ..].  The
+ * prior mean is shared (K doubles) when mean_per_group == 0, else G x K. */
+int orc_logpost_grad_groups(const void* X, int dtype, int64_t ldx, const float* scale,
+                            const uint8_t* y, const int64_t* offsets, int G, int K,
+                            const double* betas, double prec, const double* mean,
+                            int mean_per_group, double* out) {
+    size_t es = dtype == ORC_F64 ? 8 : dtype == ORC_F32 ? 4 : dtype == ORC_BF16 ? 2 : 1;
+    for (int g = 0; g < G; ++g) {
+        int64_t a = offsets[g], b = offsets[g + 1];
+        if (b < a) return -1;
+        const char* Xg = (const char*)X + (size_t)(a * ldx) * es;
+        const double* mg = mean ? (mean_per_group ? mean + (int64_t)g * K : mean) : NULL;
+        int rc = orc_logpost_grad(Xg, dtype, ldx, scale, y + a, b - a, K,
+                                  betas + (int64_t)g * K, prec, mg,
+                                  out + (int64_t)g * (1 + K));
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* ----------------------------------------------------------------- encoders */
+
+uint16_t orc_bf16_from_float(float v) {
+    uint32_t bits;
+    memcpy(&bits, &v, 4);
+    if ((bits & 0x7F800000u) == 0x7F800000u && (bits & 0x007FFFFFu))
+        return (uint16_t)((bits >> 16) | 0x0040u);        /* quiet NaN */
+    uint32_t keep = bits >> 16, rest = bits & 0xFFFFu;
+    if (rest > 0x8000u || (rest == 0x8000u && (keep & 1u))) keep += 1u;
+    return (uint16_t)keep;
+}
+
+/* Nearest FP8 E4M3FN code to v (ties to even), saturating at +-448. */
+uint8_t orc_fp8_from_float(float v) {
+    if (isnan(v)) return 0x7F;
+    uint8_t sign = signbit(v) ? 0x80 : 0x00;
+    double a = fabs((double)v);
+    if (a >= 448.0) return sign | 0x7E;
+    if (a < ldexp(1.0, -6)) {                  /* subnormal range: steps of 2^-9 */
+        double m = nearbyint(ldexp(a, 9));     /* 0 .. 8; 8 is the smallest normal */
+        return sign | (uint8_t)m;
+    }
+    int e2;
+    double fr = frexp(a, &e2);                 /* a = fr * 2^e2, fr in [0.5, 1) */
+    int e = e2 - 1;                            /* a = (2 fr) * 2^e, 2 fr in [1, 2) */
+    double m = nearbyint((2.0 * fr - 1.0) * 8.0);
+    if (m == 8.0) { m = 0.0; e += 1; }
+    if (e + 7 > 15 || (e + 7 == 15 && m == 7.0)) return sign | 0x7E;
+    return sign | (uint8_t)(((e + 7) << 3) | (int)m);
+}
+
+int orc_quantize_bf16(const float* X, int64_t N, int K, int64_t ldx,
+                      uint16_t* Q, int64_t ldq) {
+    if (K < 1 || N < 0 || ldx < K || ldq < K) return -1;
+    for (int64_t n = 0; n < N; ++n)
+        for (int k = 0; k < K; ++k) Q[n * ldq + k] = orc_bf16_from_float(X[n * ldx + k]);
+    return 0;
+}
+
+int orc_fp8_col_scales(const float* X, int64_t N, int K, int64_t ldx, float* scale) {
+    if (K < 1 || N < 0 || ldx < K) return -1;
+    for (int k = 0; k < K; ++k) {
+        float amax = 0.0f;
+        for (int64_t n = 0; n < N; ++n) {
+            float a = fabsf(X[n * ldx + k]);
+            if (a > amax) amax = a;
+        }
+        scale[k] = amax > 0.0f ? amax / 448.0f : 1.0f;
+    }
+    return 0;
+}
+
+int orc_quantize_fp8(const float* X, int64_t N, int K, int64_t ldx,
+                     const float* scale, uint8_t* Q, int64_t ldq) {
+    if (K < 1 || N < 0 || ldx < K || ldq < K) return -1;
+    for (int64_t n = 0; n < N; ++n)
+        for (int k = 0; k < K; ++k) {
+            float v = X[n * ldx + k] / scale[k];
+            Q[n * ldq + k] = orc_fp8_from_float(v);
+        }
+    return 0;
+}
