@@ -1,0 +1,189 @@
+/*
+ * glm.h -- C interface of the MI355X (gfx950) library that evaluates the
+ * Bayesian logistic-regression log-posterior and its gradient in one fused
+ * pass over a tall design matrix.
+ *
+ * The quantity (Mahani & Sharabiani, "SIMD Parallel MCMC Sampling with
+ * Applications for Big-Data Bayesian Analytics"):
+ *
+ *   u_n  = x_n . beta                                   (the "LA map", Sec. 3.2)
+ *   f    = sum_n [ y_n u_n - softplus(u_n) ]            (Sec. 3.1.1, eq-loglike-binlogit,
+ *          - prec/2 |beta - m|^2                         rewritten; Gaussian prior on beta)
+ *   g    = sum_n (y_n - sigmoid(u_n)) x_n               (Sec. 4.2, eq-grad-expanded /
+ *          - prec (beta - m)                             eq-grad-compact: X^t g_f)
+ *
+ * The paper's routine takes beta, X, y, N, K and returns f while writing g
+ * (Sec. 4.2, the loglike_fg routines); glm_logpost_grad keeps that contract
+ * with device buffers and an explicit stream, glm_logpost_grad_host keeps it
+ * with host buffers.  The Gaussian prior's parameters are left open in
+ * Sec. 3.1.1; here it is N(m, prec^-1 I) with the normalising constant
+ * dropped, so f(0) = -N ln 2 when m = 0.
+ *
+ * Conventions for every call:
+ *   - Every function returns a glm_status: GLM_OK (0), GLM_PENDING (1, only
+ *     from glm_server_poll) or a negative error code.  On an error nothing is
+ *     launched and no output is written; glm_last_error() returns a message
+ *     describing the last error raised on the calling thread.
+ *   - "device" pointers are addresses in the GPU memory of the context's
+ *     device (hipMalloc, or a torch CUDA tensor's data_ptr()); "host"
+ *     pointers are ordinary process memory.  The library never frees memory
+ *     it did not allocate.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device-buffer calls are asynchronous and stream-ordered: the output is
+ *     valid once the stream has reached the call.
+ *   - Results are FP64.  For a fixed data set, launch plan and input, a call
+ *     is bitwise reproducible (all reductions run in a fixed order; no
+ *     floating-point atomics).
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef GLM_H
+#define GLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t glm_status;
+
+#define GLM_OK           0
+#define GLM_PENDING      1   /* glm_server_poll: the ticket is not finished yet   */
+#define GLM_EINVAL      -1   /* an argument is out of range or a pointer is NULL  */
+#define GLM_EDTYPE      -2   /* unknown storage dtype                               */
+#define GLM_EHIP        -3   /* a HIP runtime call or kernel launch failed          */
+#define GLM_ENOTFOUND   -4   /* unknown data set id, group set or ticket            */
+#define GLM_EBUDGET     -5   /* a data set does not fit the server's HBM budget     */
+#define GLM_ECANCELLED  -6   /* the server was destroyed before the ticket finished */
+#define GLM_EAGAIN      -7   /* the server's request ring is full; retry            */
+#define GLM_ENOMEM      -8   /* device or host allocation failed                    */
+
+/* Storage type of X.  F64 and F32 are IEEE binary64 / binary32; BF16 is the
+ * upper half of a binary32; FP8_E4M3 is the OCP E4M3FN byte (bias 7, max
+ * +-448, no infinities) multiplied by a per-column FP32 scale. */
+typedef enum {
+    GLM_F64 = 0,
+    GLM_F32 = 1,
+    GLM_BF16 = 2,
+    GLM_FP8_E4M3 = 3
+} glm_dtype;
+
+/* Largest number of columns K any entry point accepts. */
+#define GLM_K_MAX 4096
+
+typedef struct glm_ctx glm_ctx;
+typedef int64_t glm_dataset_id;
+
+/* A data set: X (N x K, row-major, element (n,k) at X[n*ldx + k]) and the
+ * binary response y.  All pointers are device pointers owned by the caller,
+ * who keeps them alive and unchanged until the data set is unregistered.
+ *   X          device, N*ldx elements of dtype (may be NULL when N == 0)
+ *   ldx        leading dimension in elements, ldx >= K
+ *   dtype      a glm_dtype
+ *   col_scale  device, K FP32 scales s_k (value = code * s_k); FP8_E4M3 only,
+ *              must be NULL for the other dtypes
+ *   y          device, N bytes, each 0 or 1 (other values: result undefined)
+ *   N          rows, N >= 0 (N == 0 evaluates the prior alone)
+ *   K          columns, 1 <= K <= GLM_K_MAX
+ * X must be aligned to its element size. */
+typedef struct {
+    const void* X;
+    int64_t ldx;
+    int32_t dtype;
+    const float* col_scale;
+    const uint8_t* y;
+    int64_t N;
+    int32_t K;
+} glm_dataset_desc;
+
+/* Gaussian prior N(m, prec^-1 I) on beta (Sec. 3.1.1 leaves it open).
+ *   prec   precision 1/sigma^2 >= 0 (0 = flat prior)
+ *   mean   NULL (zero mean), or K doubles (device for device-buffer calls,
+ *          host for the _host call); for glm_logpost_grad_batched, G x K
+ *          doubles when mean_per_group != 0. */
+typedef struct {
+    double prec;
+    const double* mean;
+    int32_t mean_per_group;
+} glm_prior;
+
+/* ------------------------------------------------------------------ context */
+
+/* Creates a context on HIP device `device` (ordinal).  The context owns the
+ * per-stream scratch buffers (partial sums and completion counters) and the
+ * launch plans.  Errors: GLM_EINVAL (out NULL, bad ordinal), GLM_EHIP. */
+glm_status glm_create(int device, glm_ctx** out);
+
+/* Frees everything the context allocated, after synchronising its device.
+ * Data sets and group sets still registered are released (not the caller's
+ * buffers).  NULL is accepted. */
+glm_status glm_destroy(glm_ctx* ctx);
+
+/* Message for the last error raised on the calling thread ("" if none). */
+const char* glm_last_error(void);
+
+/* --------------------------------------------------------------- data sets */
+
+/* Validates desc, picks the launch plan (kernel instance from dtype, K and
+ * alignment; grid size from the device's compute-unit count and the tuning
+ * cache) and returns an id.  The data are not read here.  Errors: GLM_EINVAL
+ * (N < 0, K out of range, ldx < K, NULL/misaligned X or y with N > 0,
+ * col_scale missing for FP8 or present otherwise), GLM_EDTYPE. */
+glm_status glm_dataset_register(glm_ctx* ctx, const glm_dataset_desc* desc,
+                                glm_dataset_id* out);
+
+/* Forgets a data set.  Calls already enqueued on a stream still read the
+ * caller's buffers, so synchronise before freeing them.  GLM_ENOTFOUND. */
+glm_status glm_dataset_unregister(glm_ctx* ctx, glm_dataset_id id);
+
+/* ------------------------------------------------------------ plain call */
+
+/* f and g at one beta (Sec. 4.2): one fused kernel launch streams X once,
+ * computes u, the transcendental map and the X^t contribution per row tile,
+ * and its last block to finish adds the partial sums of all blocks in a fixed
+ * order and the prior.
+ *   beta   device, K doubles
+ *   prior  host struct; prior->mean is a device pointer (K doubles) or NULL
+ *   out    device, 1 + K doubles: out[0] = f, out[1 + k] = g_k
+ *   stream hipStream_t or NULL
+ * Calls on one stream run one after another; concurrent calls on different
+ * streams are safe (each stream has its own scratch).  A NaN or Inf in beta
+ * propagates into the result.  Errors: GLM_EINVAL, GLM_ENOTFOUND, GLM_EHIP,
+ * GLM_ENOMEM (scratch growth). */
+glm_status glm_logpost_grad(glm_ctx* ctx, glm_dataset_id id, const double* beta,
+                            const glm_prior* prior, double* out, void* stream);
+
+/* Host-buffer form mirroring the paper's routine: copies beta (and the
+ * prior mean, if any) to the device, launches, copies f and g back and waits.
+ *   beta_host  K doubles;  prior->mean host K doubles or NULL
+ *   f          host double;  g_host  host K doubles (may be NULL)
+ * Uses the context's own stream.  Same errors as glm_logpost_grad. */
+glm_status glm_logpost_grad_host(glm_ctx* ctx, glm_dataset_id id,
+                                 const double* beta_host, const glm_prior* prior,
+                                 double* f, double* g_host);
+
+/* ----------------------------------------------------- storage conversions */
+
+/* BF16 copy of an FP32 matrix, round to nearest even (NaN stays NaN).
+ *   X device N x K FP32 (leading dim ldx); Q device N x K uint16 (leading dim ldq).
+ * Errors: GLM_EINVAL, GLM_EHIP. */
+glm_status glm_quantize_bf16(glm_ctx* ctx, const float* X, int64_t N, int32_t K,
+                             int64_t ldx, uint16_t* Q, int64_t ldq, void* stream);
+
+/* Per-column FP8 scales s_k = max_n |x_nk| / 448 in FP32 (1 for an all-zero
+ * column), so that the largest magnitude of each column maps to the largest
+ * finite E4M3FN value.  X device N x K FP32; scale device K floats. */
+glm_status glm_fp8_col_scales(glm_ctx* ctx, const float* X, int64_t N, int32_t K,
+                              int64_t ldx, float* scale, void* stream);
+
+/* FP8 E4M3FN codes of x_nk / s_k (FP32 division), round to nearest even,
+ * saturating at +-448.  Q device N x K bytes (leading dim ldq). */
+glm_status glm_quantize_fp8(glm_ctx* ctx, const float* X, int64_t N, int32_t K,
+                            int64_t ldx, const float* scale, uint8_t* Q, int64_t ldq,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLM_H */

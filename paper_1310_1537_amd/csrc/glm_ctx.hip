@@ -1,0 +1,147 @@
+// Context, data-set registry, per-stream scratch and error reporting.
+#include "runtime.hpp"
+
+#include <cstring>
+
+namespace glmrt {
+
+static thread_local char t_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_err, sizeof(t_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { t_err[0] = 0; }
+
+glm_status use_device(glm_ctx* ctx) {
+    GLM_HIP_CHECK(hipSetDevice(ctx->device));
+    return GLM_OK;
+}
+
+// Tickets must start at zero; a fill kernel keeps the scratch set-up free of
+// memset nodes if the caller captures the first call into a graph.
+__global__ void fill_u32(unsigned* p, size_t n, unsigned v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+glm_status get_scratch(glm_ctx* ctx, void* stream, size_t n_partials, size_t n_gpart,
+                       size_t n_counters, Scratch** out) {
+    Scratch& s = ctx->scratch[stream];
+    if (s.base && s.cap_partials >= n_partials && s.cap_gpart >= n_gpart &&
+        s.cap_counters >= n_counters) {
+        *out = &s;
+        return GLM_OK;
+    }
+    // grow with headroom
+    size_t np = std::max(n_partials, s.cap_partials) * 5 / 4 + 1024;
+    size_t ng = std::max(n_gpart, s.cap_gpart) * 5 / 4 + 1024;
+    size_t nc = std::max(n_counters, s.cap_counters) * 5 / 4 + 64;
+    size_t bytes = (np + ng) * sizeof(double) + nc * sizeof(unsigned);
+    if (s.base) {
+        // earlier launches on any stream may still use the old buffer
+        GLM_HIP_CHECK(hipDeviceSynchronize());
+        GLM_HIP_CHECK(hipFree(s.base));
+        s = Scratch{};
+    }
+    void* base = nullptr;
+    hipError_t e = hipMalloc(&base, bytes);
+    if (e != hipSuccess) GLM_FAIL(GLM_ENOMEM, "scratch allocation of %zu bytes failed: %s", bytes,
+                                  hipGetErrorString(e));
+    s.base = base;
+    s.bytes = bytes;
+    s.partials = (double*)base;
+    s.gpart = s.partials + np;
+    s.counters = (unsigned*)(s.gpart + ng);
+    s.cap_partials = np;
+    s.cap_gpart = ng;
+    s.cap_counters = nc;
+    hipLaunchKernelGGL(fill_u32, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, s.counters, nc, 0u);
+    GLM_HIP_CHECK(hipGetLastError());
+    *out = &s;
+    return GLM_OK;
+}
+
+}  // namespace glmrt
+
+using namespace glmrt;
+
+extern "C" {
+
+const char* glm_last_error(void) { return t_err; }
+
+glm_status glm_create(int device, glm_ctx** out) {
+    clear_error();
+    if (!out) GLM_FAIL(GLM_EINVAL, "glm_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    GLM_HIP_CHECK(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) GLM_FAIL(GLM_EINVAL, "glm_create: device %d of %d", device, n);
+    GLM_HIP_CHECK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    GLM_HIP_CHECK(hipGetDeviceProperties(&prop, device));
+    std::unique_ptr<glm_ctx> c(new glm_ctx);
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    GLM_HIP_CHECK(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+    *out = c.release();
+    return GLM_OK;
+}
+
+glm_status glm_destroy(glm_ctx* ctx) {
+    clear_error();
+    if (!ctx) return GLM_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (auto& kv : ctx->scratch)
+        if (kv.second.base) hipFree(kv.second.base);
+    if (ctx->h_stage) hipHostFree(ctx->h_stage);
+    if (ctx->d_stage) hipFree(ctx->d_stage);
+    if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+    return GLM_OK;
+}
+
+glm_status glm_dataset_register(glm_ctx* ctx, const glm_dataset_desc* d, glm_dataset_id* out) {
+    clear_error();
+    if (!ctx || !d || !out) GLM_FAIL(GLM_EINVAL, "glm_dataset_register: NULL argument");
+    const int es = elem_size(d->dtype);
+    if (!es) GLM_FAIL(GLM_EDTYPE, "glm_dataset_register: unknown dtype %d", d->dtype);
+    if (d->N < 0) GLM_FAIL(GLM_EINVAL, "glm_dataset_register: N = %lld < 0", (long long)d->N);
+    if (d->K < 1 || d->K > GLM_K_MAX)
+        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: K = %d outside [1, %d]", d->K, GLM_K_MAX);
+    if (d->ldx < d->K)
+        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: ldx = %lld < K = %d", (long long)d->ldx, d->K);
+    if (d->N > 0 && (!d->X || !d->y)) GLM_FAIL(GLM_EINVAL, "glm_dataset_register: X or y is NULL");
+    if (d->X && ((uintptr_t)d->X % es))
+        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: X not aligned to its %d-byte element", es);
+    if (d->dtype == GLM_FP8_E4M3 && !d->col_scale)
+        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: FP8 data needs col_scale");
+    if (d->dtype != GLM_FP8_E4M3 && d->col_scale)
+        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: col_scale is only for FP8 data");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Dataset ds;
+    ds.d = *d;
+    glm_status st = make_plan(ctx, *d, &ds.plan);
+    if (st != GLM_OK) return st;
+    const int64_t id = ctx->next_id++;
+    ctx->datasets[id] = ds;
+    *out = id;
+    return GLM_OK;
+}
+
+glm_status glm_dataset_unregister(glm_ctx* ctx, glm_dataset_id id) {
+    clear_error();
+    if (!ctx) GLM_FAIL(GLM_EINVAL, "glm_dataset_unregister: ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->datasets.erase(id)) GLM_FAIL(GLM_ENOTFOUND, "glm_dataset_unregister: unknown id %lld",
+                                           (long long)id);
+    return GLM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+// Plain entry points: one data set, one beta per launch.
+#include <cmath>
+#include <cstring>
+
+#include "fg_kernel.hpp"
+#include "runtime.hpp"
+
+namespace glmrt {
+
+namespace {
+
+constexpr int WPB = 4;
+
+struct Inst {
+    const void* fn;
+    int R;
+};
+
+template <int DT, int LPR, int CPL>
+Inst inst() {
+    // about 64 elements of X per lane per batch
+    constexpr int VE = 16 / glmk::ElemSize<DT>::v;
+    constexpr int RE = DT == glmk::DT_F64 ? 16 : 64 / VE;
+    constexpr int R = RE / CPL > 0 ? RE / CPL : 1;
+    return Inst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, R, WPB>), R};
+}
+
+template <int DT>
+Inst pick(int lpr, int cpl) {
+    if (cpl == 1) {
+        switch (lpr) {
+        case 1: return inst<DT, 1, 1>();
+        case 2: return inst<DT, 2, 1>();
+        case 4: return inst<DT, 4, 1>();
+        case 8: return inst<DT, 8, 1>();
+        case 16: return inst<DT, 16, 1>();
+        case 32: return inst<DT, 32, 1>();
+        case 64: return inst<DT, 64, 1>();
+        }
+    } else if (lpr == 64) {
+        if (cpl == 2) return inst<DT, 64, 2>();
+        if (cpl == 4) return inst<DT, 64, 4>();
+    }
+    return Inst{nullptr, 0};
+}
+
+Inst pick_any(int dt, int lpr, int cpl) {
+    switch (dt) {
+    case GLM_F64: return pick<glmk::DT_F64>(lpr, cpl);
+    case GLM_F32: return pick<glmk::DT_F32>(lpr, cpl);
+    case GLM_BF16: return pick<glmk::DT_BF16>(lpr, cpl);
+    case GLM_FP8_E4M3: return pick<glmk::DT_FP8>(lpr, cpl);
+    }
+    return Inst{nullptr, 0};
+}
+
+int pow2ceil(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
+    const int es = elem_size(d.dtype);
+    const int ve = 16 / es;
+    const bool vec_ok = (d.K * es) % 16 == 0 && (d.ldx * es) % 16 == 0 &&
+                        ((uintptr_t)d.X % 16) == 0;
+    if (!vec_ok)
+        GLM_FAIL(GLM_EINVAL,
+                 "plan: rows must be whole 16-byte chunks (K*%d and ldx*%d multiples of 16, X "
+                 "16-byte aligned)",
+                 es, es);
+    const int nc = d.K / ve;
+    Plan p;
+    p.kind = 0;
+    p.lpr = std::min(64, pow2ceil(nc));
+    p.cpl = nc <= 64 ? 1 : pow2ceil((nc + 63) / 64);
+    if (p.cpl > 4) GLM_FAIL(GLM_EINVAL, "plan: K = %d too wide for dtype %d", d.K, d.dtype);
+    Inst in = pick_any(d.dtype, p.lpr, p.cpl);
+    if (!in.fn) GLM_FAIL(GLM_EINVAL, "plan: no kernel instance for K = %d", d.K);
+    p.fn = in.fn;
+    p.rows_per_lane = in.R;
+    p.wpb = WPB;
+    const int64_t wave_rows = (int64_t)in.R * (64 / p.lpr);
+    const int64_t block_rows = wave_rows * p.wpb;
+    const int64_t target = (int64_t)ctx->num_cu * 4;
+    int64_t nb = (d.N + block_rows - 1) / block_rows;
+    nb = std::max<int64_t>(1, std::min(nb, target));
+    int64_t rpb = (d.N + nb - 1) / nb;
+    rpb = (rpb + block_rows - 1) / block_rows * block_rows;
+    if (d.N == 0) rpb = 0;
+    p.rows_per_block = rpb;
+    p.nblocks = rpb ? (int)((d.N + rpb - 1) / rpb) : 1;
+    p.group = std::max(1, (int)std::ceil(std::sqrt((double)p.nblocks)));
+    *plan = p;
+    return GLM_OK;
+}
+
+static glm_status launch_plain(glm_ctx* ctx, const Dataset& ds, const double* beta,
+                               const glm_prior* prior, double* out, void* stream) {
+    const Plan& pl = ds.plan;
+    const int K1 = ds.d.K + 1;
+    const int ngroups = (pl.nblocks + pl.group - 1) / pl.group;
+    Scratch* s = nullptr;
+    glm_status st = get_scratch(ctx, stream, (size_t)pl.nblocks * K1, (size_t)ngroups * K1,
+                                (size_t)ngroups + 1, &s);
+    if (st != GLM_OK) return st;
+    glmk::FgParams p;
+    p.X = static_cast<const unsigned char*>(ds.d.X);
+    p.ldx = ds.d.ldx;
+    p.y = ds.d.y;
+    p.N = ds.d.N;
+    p.K = ds.d.K;
+    p.scale = ds.d.col_scale;
+    p.beta = beta;
+    p.mean = prior->mean;
+    p.prec = prior->prec;
+    p.out = out;
+    p.partials = s->partials;
+    p.gpart = s->gpart;
+    p.counters = s->counters;
+    p.nblocks = pl.nblocks;
+    p.group = pl.group;
+    p.rows_per_block = pl.rows_per_block;
+    void* args[] = {&p};
+    GLM_HIP_CHECK(hipLaunchKernel(pl.fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0,
+                                  (hipStream_t)stream));
+    return GLM_OK;
+}
+
+}  // namespace glmrt
+
+using namespace glmrt;
+
+extern "C" {
+
+glm_status glm_logpost_grad(glm_ctx* ctx, glm_dataset_id id, const double* beta,
+                            const glm_prior* prior, double* out, void* stream) {
+    clear_error();
+    if (!ctx || !beta || !prior || !out) GLM_FAIL(GLM_EINVAL, "glm_logpost_grad: NULL argument");
+    if (!(prior->prec >= 0.0)) GLM_FAIL(GLM_EINVAL, "glm_logpost_grad: prior precision < 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->datasets.find(id);
+    if (it == ctx->datasets.end())
+        GLM_FAIL(GLM_ENOTFOUND, "glm_logpost_grad: unknown data set %lld", (long long)id);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    return launch_plain(ctx, it->second, beta, prior, out, stream);
+}
+
+glm_status glm_logpost_grad_host(glm_ctx* ctx, glm_dataset_id id, const double* beta_host,
+                                 const glm_prior* prior, double* f, double* g_host) {
+    clear_error();
+    if (!ctx || !beta_host || !prior || !f)
+        GLM_FAIL(GLM_EINVAL, "glm_logpost_grad_host: NULL argument");
+    if (!(prior->prec >= 0.0)) GLM_FAIL(GLM_EINVAL, "glm_logpost_grad_host: prior precision < 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->datasets.find(id);
+    if (it == ctx->datasets.end())
+        GLM_FAIL(GLM_ENOTFOUND, "glm_logpost_grad_host: unknown data set %lld", (long long)id);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    const int K = it->second.d.K;
+    const size_t need = 3 * (size_t)K + 1;
+    if (ctx->stage_cap < need) {
+        if (ctx->h_stage) hipHostFree(ctx->h_stage);
+        if (ctx->d_stage) hipFree(ctx->d_stage);
+        ctx->h_stage = nullptr;
+        ctx->d_stage = nullptr;
+        ctx->stage_cap = 0;
+        GLM_HIP_CHECK(hipHostMalloc((void**)&ctx->h_stage, need * sizeof(double)));
+        GLM_HIP_CHECK(hipMalloc((void**)&ctx->d_stage, need * sizeof(double)));
+        ctx->stage_cap = need;
+    }
+    double* hb = ctx->h_stage;
+    double* db = ctx->d_stage;
+    std::memcpy(hb, beta_host, K * sizeof(double));
+    size_t nin = K;
+    glm_prior pd = *prior;
+    if (prior->mean) {
+        std::memcpy(hb + K, prior->mean, K * sizeof(double));
+        pd.mean = db + K;
+        nin = 2 * (size_t)K;
+    }
+    hipStream_t s = ctx->own_stream;
+    GLM_HIP_CHECK(hipMemcpyAsync(db, hb, nin * sizeof(double), hipMemcpyHostToDevice, s));
+    st = launch_plain(ctx, it->second, db, &pd, db + 2 * K, s);
+    if (st != GLM_OK) return st;
+    GLM_HIP_CHECK(hipMemcpyAsync(hb + 2 * K, db + 2 * K, (K + 1) * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    GLM_HIP_CHECK(hipStreamSynchronize(s));
+    *f = hb[2 * K];
+    if (g_host) std::memcpy(g_host, hb + 2 * K + 1, K * sizeof(double));
+    return GLM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Host runtime shared by the entry points: context, data-set registry,
+// per-stream scratch, error reporting.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "glm.h"
+
+namespace glmrt {
+
+// ------------------------------------------------------------ errors
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define GLM_FAIL(code, ...)            \
+    do {                               \
+        ::glmrt::set_error(__VA_ARGS__); \
+        return (code);                 \
+    } while (0)
+
+#define GLM_HIP_CHECK(expr)                                                          \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            GLM_FAIL(GLM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+inline int elem_size(int dtype) {
+    switch (dtype) {
+    case GLM_F64: return 8;
+    case GLM_F32: return 4;
+    case GLM_BF16: return 2;
+    case GLM_FP8_E4M3: return 1;
+    }
+    return 0;
+}
+
+// ------------------------------------------------------------ launch plan
+
+// Which kernel instance and grid shape a data set is evaluated with.
+struct Plan {
+    int kind = 0;          // 0 = vector-chunk fused kernel, 1 = generic any-K kernel
+    int lpr = 1;           // lanes per row
+    int cpl = 1;           // 16-byte chunks per lane per row
+    int rows_per_lane = 1; // R: row slots per lane per batch
+    int wpb = 4;           // waves per block
+    int nblocks = 1;
+    int group = 32;        // blocks per merge group
+    int64_t rows_per_block = 0;
+    const void* fn = nullptr;   // __global__ function
+};
+
+struct Dataset {
+    glm_dataset_desc d;
+    Plan plan;
+};
+
+// Device scratch of one stream: block partials, group partials, tickets.
+struct Scratch {
+    void* base = nullptr;
+    size_t bytes = 0;
+    double* partials = nullptr;
+    double* gpart = nullptr;
+    unsigned* counters = nullptr;
+    size_t cap_partials = 0;   // doubles
+    size_t cap_gpart = 0;      // doubles
+    size_t cap_counters = 0;   // unsigned
+};
+
+struct GroupSet;   // defined by the batched entry point
+
+}  // namespace glmrt
+
+struct glm_ctx {
+    int device = 0;
+    int num_cu = 256;
+    std::string arch;
+    std::mutex mu;
+    int64_t next_id = 1;
+    std::unordered_map<int64_t, glmrt::Dataset> datasets;
+    std::map<void*, glmrt::Scratch> scratch;   // keyed by stream
+    hipStream_t own_stream = nullptr;
+    // host-call staging (pinned) and device buffers
+    double* h_stage = nullptr;
+    double* d_stage = nullptr;
+    size_t stage_cap = 0;   // doubles
+};
+
+namespace glmrt {
+
+// Scratch for `stream` with room for the given sizes; grows (synchronising
+// the device) when needed and zeroes the tickets of new memory.
+glm_status get_scratch(glm_ctx* ctx, void* stream, size_t n_partials, size_t n_gpart,
+                       size_t n_counters, Scratch** out);
+
+// Sets the device of ctx current on this thread.
+glm_status use_device(glm_ctx* ctx);
+
+// Plan for a data set (defined with the kernel table).
+glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan);
+
+}  // namespace glmrt

@@ -1,0 +1,197 @@
+"""Python binding of the C interface in include/glm.h (argument marshalling
+only: every step of the computation runs in the HIP library).
+
+The functions carry the C names.  Device buffers are passed as torch CUDA
+tensors (their ``data_ptr()``) or as integer addresses; streams as a
+``torch.cuda.Stream``, an integer hipStream_t, or None (the null stream).
+Non-OK status codes raise :class:`GlmError` with the library's message,
+except ``GLM_PENDING`` from ``glm_server_poll``, which is returned.
+
+The library is loaded from the package directory; if it has not been built
+the import fails loudly -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime the library shares
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglm_hip.so")
+
+GLM_OK, GLM_PENDING = 0, 1
+GLM_EINVAL, GLM_EDTYPE, GLM_EHIP, GLM_ENOTFOUND = -1, -2, -3, -4
+GLM_EBUDGET, GLM_ECANCELLED, GLM_EAGAIN, GLM_ENOMEM = -5, -6, -7, -8
+GLM_F64, GLM_F32, GLM_BF16, GLM_FP8_E4M3 = 0, 1, 2, 3
+GLM_K_MAX = 4096
+
+STATUS_NAMES = {0: "GLM_OK", 1: "GLM_PENDING", -1: "GLM_EINVAL", -2: "GLM_EDTYPE",
+                -3: "GLM_EHIP", -4: "GLM_ENOTFOUND", -5: "GLM_EBUDGET",
+                -6: "GLM_ECANCELLED", -7: "GLM_EAGAIN", -8: "GLM_ENOMEM"}
+
+
+class GlmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class glm_dataset_desc(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("col_scale", ctypes.c_void_p), ("y", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("K", ctypes.c_int32)]
+
+
+class glm_prior(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_double), ("mean", ctypes.c_void_p),
+                ("mean_per_group", ctypes.c_int32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_SIGS = {
+    "glm_create": [ctypes.c_int, _PP],
+    "glm_destroy": [_P],
+    "glm_dataset_register": [_P, ctypes.POINTER(glm_dataset_desc), ctypes.POINTER(_I64)],
+    "glm_dataset_unregister": [_P, _I64],
+    "glm_logpost_grad": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P],
+    "glm_logpost_grad_host": [_P, _I64, _P, ctypes.POINTER(glm_prior), ctypes.POINTER(_D), _P],
+    "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
+    "glm_fp8_col_scales": [_P, _P, _I64, _I32, _I64, _P, _P],
+    "glm_quantize_fp8": [_P, _P, _I64, _I32, _I64, _P, _P, _I64, _P],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int32
+_lib.glm_last_error.argtypes = []
+_lib.glm_last_error.restype = ctypes.c_char_p
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def glm_last_error() -> str:
+    return _lib.glm_last_error().decode()
+
+
+def _check(st: int, allow_pending: bool = False) -> int:
+    if st == GLM_OK or (allow_pending and st == GLM_PENDING):
+        return st
+    raise GlmError(st, glm_last_error())
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    raise TypeError(f"cannot pass {type(x)} as a device pointer")
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _dtype_code(t: torch.Tensor, dtype: int | None) -> int:
+    if dtype is not None:
+        return dtype
+    return {torch.float64: GLM_F64, torch.float32: GLM_F32, torch.bfloat16: GLM_BF16,
+            torch.uint16: GLM_BF16, torch.float8_e4m3fn: GLM_FP8_E4M3,
+            torch.uint8: GLM_FP8_E4M3}[t.dtype]
+
+
+# ---------------------------------------------------------------- context
+
+def glm_create(device: int = 0) -> int:
+    out = ctypes.c_void_p()
+    _check(_lib.glm_create(device, ctypes.byref(out)))
+    return out.value
+
+
+def glm_destroy(ctx: int) -> None:
+    _check(_lib.glm_destroy(ctx))
+
+
+# ---------------------------------------------------------------- data sets
+
+def make_desc(X, y, N=None, K=None, ldx=None, dtype=None, col_scale=None) -> glm_dataset_desc:
+    """Descriptor for a row-major X (2-D tensor, or address with explicit
+    N/K/ldx/dtype) and its uint8 response y."""
+    if isinstance(X, torch.Tensor):
+        assert X.dim() == 2 and X.stride(1) == 1
+        N = X.shape[0] if N is None else N
+        K = X.shape[1] if K is None else K
+        ldx = X.stride(0) if ldx is None else ldx
+        dtype = _dtype_code(X, dtype)
+    return glm_dataset_desc(_ptr(X), ldx, dtype, _ptr(col_scale), _ptr(y), N, K)
+
+
+def glm_dataset_register(ctx: int, desc: glm_dataset_desc) -> int:
+    out = ctypes.c_int64()
+    _check(_lib.glm_dataset_register(ctx, ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def glm_dataset_unregister(ctx: int, ds: int) -> None:
+    _check(_lib.glm_dataset_unregister(ctx, ds))
+
+
+def make_prior(prec: float, mean=None, per_group: bool = False) -> glm_prior:
+    return glm_prior(prec, _ptr(mean), int(per_group))
+
+
+# ---------------------------------------------------------------- evaluation
+
+def glm_logpost_grad(ctx: int, ds: int, beta, prior: glm_prior, out, stream=None) -> None:
+    _check(_lib.glm_logpost_grad(ctx, ds, _ptr(beta), ctypes.byref(prior), _ptr(out),
+                                 _stream(stream)))
+
+
+def glm_logpost_grad_host(ctx: int, ds: int, beta_host, prior: glm_prior, g_host=None):
+    """beta_host / prior.mean / g_host: numpy float64 arrays (host).  Returns f."""
+    import numpy as np
+    b = np.ascontiguousarray(beta_host, np.float64)
+    f = ctypes.c_double()
+    gp = None if g_host is None else g_host.ctypes.data_as(ctypes.c_void_p)
+    _check(_lib.glm_logpost_grad_host(ctx, ds, b.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(prior), ctypes.byref(f), gp))
+    return f.value
+
+
+# ---------------------------------------------------------------- conversions
+
+def glm_quantize_bf16(ctx: int, X, Q, stream=None) -> None:
+    N, K = X.shape
+    _check(_lib.glm_quantize_bf16(ctx, _ptr(X), N, K, X.stride(0), _ptr(Q), Q.stride(0),
+                                  _stream(stream)))
+
+
+def glm_fp8_col_scales(ctx: int, X, scale, stream=None) -> None:
+    N, K = X.shape
+    _check(_lib.glm_fp8_col_scales(ctx, _ptr(X), N, K, X.stride(0), _ptr(scale),
+                                   _stream(stream)))
+
+
+def glm_quantize_fp8(ctx: int, X, scale, Q, stream=None) -> None:
+    N, K = X.shape
+    _check(_lib.glm_quantize_fp8(ctx, _ptr(X), N, K, X.stride(0), _ptr(scale), _ptr(Q),
+                                 Q.stride(0), _stream(stream)))
+
+
+def exported_symbols() -> list[str]:
+    return sorted(_SIGS) + ["glm_last_error"]

@@ -1,0 +1,176 @@
+"""GPU parity of the plain fused evaluation (glm_logpost_grad) against the
+FP64 oracle, through the C interface."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+if torch.cuda.is_available():
+    from gpu_helpers import DEV, Ctx, check_against_oracle, eval_gpu, to_dev  # noqa: E402
+    from paper_1310_1537_amd import glm  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Ctx()
+    yield c.h
+    c.close()
+
+
+def _rand(N, K, seed, dtype=np.float32, nbin=0):
+    g = np.random.default_rng(seed)
+    X = g.standard_normal((N, K)).astype(dtype)
+    if nbin:
+        X[:, K - nbin:] = (g.random((N, nbin)) < 0.3)
+    beta = g.standard_normal(K) / math.sqrt(K)
+    y = (g.random(N) < 1.0 / (1.0 + np.exp(-(X.astype(np.float64) @ beta)))).astype(np.uint8)
+    return X, y, beta + 0.1 * g.standard_normal(K)
+
+
+def test_small_f64_workload_every_point(ctx):
+    """N=10,000, K=20, FP64 X: all 100 seeded points and beta = 0;
+    f within 1e-12 and g within 1e-10 (norm) of the oracle."""
+    w = synth.plain_small(n_evals=100)
+    X, y = to_dev(w.X), to_dev(w.y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
+    worst_f = worst_g = 0.0
+    for beta in w.betas:
+        f, g = eval_gpu(ctx, X, y, beta, w.prec, ds=ds)
+        ef, eg = check_against_oracle(f, g, w.X, w.y, beta, w.prec, storage="f64")
+        worst_f, worst_g = max(worst_f, ef), max(worst_g, eg)
+    assert worst_f < 1e-12 and worst_g < 1e-10, (worst_f, worst_g)
+    f0, _ = eval_gpu(ctx, X, y, np.zeros(20), w.prec, ds=ds)
+    assert abs(f0 + 10_000 * math.log(2.0)) < 1e-13 * 10_000
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+# K values cover every lanes-per-row / chunks-per-lane instance of FP32
+# (16-byte chunks of 4 columns): 1, 2, 4, ..., 64 lanes and 2 or 4 chunks.
+F32_K = [4, 8, 16, 32, 64, 128, 256, 512, 1024]
+N_CASES = [0, 1, 63, 64, 65, 1000, 40_003]
+
+
+@pytest.mark.parametrize("K", F32_K)
+@pytest.mark.parametrize("N", N_CASES)
+def test_f32_shapes_against_oracle(ctx, K, N):
+    X, y, beta = _rand(N, K, 1000 * K + N % 997)
+    f, g = eval_gpu(ctx, to_dev(X), to_dev(y), beta, 0.01)
+    check_against_oracle(f, g, X.astype(np.float64), y, beta, 0.01)
+
+
+@pytest.mark.parametrize("K", [2, 4, 8, 16, 32, 64, 128, 256, 512])
+@pytest.mark.parametrize("N", [0, 1, 65, 9_001])
+def test_f64_shapes_against_oracle(ctx, K, N):
+    X, y, beta = _rand(N, K, 7 * K + N, np.float64)
+    f, g = eval_gpu(ctx, to_dev(X), to_dev(y), beta, 0.5, mean=np.full(K, 0.05))
+    check_against_oracle(f, g, X, y, beta, 0.5, mean=np.full(K, 0.05), storage="f64")
+
+
+def test_prior_mean_and_precision(ctx):
+    X, y, beta = _rand(3000, 32, 5)
+    m = np.linspace(-1, 1, 32)
+    f, g = eval_gpu(ctx, to_dev(X), to_dev(y), beta, 4.0, mean=m)
+    check_against_oracle(f, g, X.astype(np.float64), y, beta, 4.0, mean=m)
+
+
+def test_padded_leading_dimension(ctx):
+    """ldx > K: only the first K columns of each row enter."""
+    X, y, beta = _rand(2000, 64, 6)
+    Xp = np.zeros((2000, 80), np.float32)
+    Xp[:, :64] = X
+    Xp[:, 64:] = 1e30                      # must never be read into the sums
+    Xt = to_dev(Xp)
+    desc = glm.make_desc(Xt, to_dev(y), K=64, ldx=80)
+    ds = glm.glm_dataset_register(ctx, desc)
+    out = torch.empty(65, dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad(ctx, ds, to_dev(beta), glm.make_prior(0.01), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    check_against_oracle(o[0], o[1:], X.astype(np.float64), y, beta, 0.01)
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+def test_bitwise_reproducible_across_calls_and_streams(ctx):
+    X, y, beta = _rand(200_000, 256, 8)
+    Xd, yd = to_dev(X), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
+    r1 = eval_gpu(ctx, Xd, yd, beta, 0.01, ds=ds)
+    r2 = eval_gpu(ctx, Xd, yd, beta, 0.01, ds=ds)
+    s = torch.cuda.Stream()
+    r3 = eval_gpu(ctx, Xd, yd, beta, 0.01, ds=ds, stream=s)
+    for r in (r2, r3):
+        assert r[0] == r1[0] and np.array_equal(r[1], r1[1])
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+def test_host_call_equals_device_call(ctx):
+    X, y, beta = _rand(5000, 48, 9)
+    Xd, yd = to_dev(X), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
+    f_d, g_d = eval_gpu(ctx, Xd, yd, beta, 0.01, ds=ds)
+    g_h = np.empty(48)
+    f_h = glm.glm_logpost_grad_host(ctx, ds, beta, glm.make_prior(0.01), g_h)
+    assert f_h == f_d and np.array_equal(g_h, g_d)
+    m = np.full(48, 0.2)
+    f_m = glm.glm_logpost_grad_host(ctx, ds, beta, glm.make_prior(2.0, m), g_h)
+    f_o, g_o = oracle.logpost_grad(X, y, beta, 2.0, m)
+    assert abs(f_m - f_o) < 1e-6 * abs(f_o)
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+def test_extreme_linear_predictor(ctx):
+    """|u| ~ 1e3 in FP32 storage: finite results equal to the oracle's."""
+    X = np.array([[1000.0, 0, 0, 0], [1000.0, 0, 0, 0], [-1000.0, 0, 0, 0], [-1000.0, 0, 0, 0]],
+                 np.float32)
+    y = np.array([1, 0, 1, 0], np.uint8)
+    f, g = eval_gpu(ctx, to_dev(X), to_dev(y), np.array([1.0, 0, 0, 0]), 0.0)
+    assert f == -2000.0 and g[0] == -2000.0 and np.all(g[1:] == 0)
+
+
+def test_status_codes(ctx):
+    X, y, _ = _rand(100, 8, 10)
+    Xd, yd = to_dev(X), to_dev(y)
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd, K=0))
+    assert e.value.status == glm.GLM_EINVAL
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd, ldx=4))
+    assert e.value.status == glm.GLM_EINVAL
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd, dtype=9))
+    assert e.value.status == glm.GLM_EDTYPE
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd, N=-1))
+    assert e.value.status == glm.GLM_EINVAL
+    out = torch.empty(9, dtype=torch.float64, device=DEV)
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_logpost_grad(ctx, 123456, to_dev(np.zeros(8)), glm.make_prior(0.0), out)
+    assert e.value.status == glm.GLM_ENOTFOUND
+    assert "unknown data set" in glm.glm_last_error()
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_dataset_unregister(ctx, 123456)
+    assert e.value.status == glm.GLM_ENOTFOUND
+
+
+def test_big_plain_workload_full_size(ctx):
+    """N=4,000,000, K=256, FP32 X (10% binary columns): trajectory points
+    against the oracle at the stated tolerances f <= 1e-9, g <= 1e-7 (norm)."""
+    w = synth.plain_big(n_evals=1000)
+    X, y = to_dev(w.X), to_dev(w.y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
+    for i in (0, 999):
+        beta = w.betas[i]
+        f, g = eval_gpu(ctx, X, y, beta, w.prec, ds=ds)
+        fo, go = oracle.logpost_grad(w.X, w.y, beta, w.prec)
+        ef = abs(f - fo) / abs(fo)
+        eg = np.linalg.norm(g - go) / np.linalg.norm(go)
+        print(f"big plain point {i}: rel err f {ef:.2e}  g {eg:.2e}", flush=True)
+        assert ef <= 1e-9 and eg <= 1e-7, (ef, eg)
+    glm.glm_dataset_unregister(ctx, ds)
