@@ -96,6 +96,8 @@ def _ptr(x) -> int | None:
         return x
     if isinstance(x, torch.Tensor):
         return x.data_ptr()
+    if hasattr(x, "ctypes") and hasattr(x, "dtype"):   # numpy array: a host pointer
+        return x.ctypes.data
     raise TypeError(f"cannot pass {type(x)} as a device pointer")
 
 
@@ -133,10 +135,14 @@ def make_desc(X, y, N=None, K=None, ldx=None, dtype=None, col_scale=None) -> glm
     """Descriptor for a row-major X (2-D tensor, or address with explicit
     N/K/ldx/dtype) and its uint8 response y."""
     if isinstance(X, torch.Tensor):
-        assert X.dim() == 2 and X.stride(1) == 1
+        assert X.dim() == 2
         N = X.shape[0] if N is None else N
         K = X.shape[1] if K is None else K
-        ldx = X.stride(0) if ldx is None else ldx
+        if X.numel() == 0:
+            ldx = K if ldx is None else ldx
+        else:
+            assert X.stride(1) == 1, "X must be row-major"
+            ldx = X.stride(0) if ldx is None else ldx
         dtype = _dtype_code(X, dtype)
     return glm_dataset_desc(_ptr(X), ldx, dtype, _ptr(col_scale), _ptr(y), N, K)
 

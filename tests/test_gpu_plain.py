@@ -86,8 +86,8 @@ def test_padded_leading_dimension(ctx):
     Xp = np.zeros((2000, 80), np.float32)
     Xp[:, :64] = X
     Xp[:, 64:] = 1e30                      # must never be read into the sums
-    Xt = to_dev(Xp)
-    desc = glm.make_desc(Xt, to_dev(y), K=64, ldx=80)
+    Xt, yt = to_dev(Xp), to_dev(y)      # the caller keeps both alive
+    desc = glm.make_desc(Xt, yt, K=64, ldx=80)
     ds = glm.glm_dataset_register(ctx, desc)
     out = torch.empty(65, dtype=torch.float64, device=DEV)
     glm.glm_logpost_grad(ctx, ds, to_dev(beta), glm.make_prior(0.01), out)
