@@ -71,7 +71,7 @@ struct FgParams {
     unsigned* counters;       // ngroups + 1 tickets, zero between launches
     int nblocks;
     int group;                // blocks per merge group
-    int64_t rows_per_block;   // contiguous row range of each block
+    int interleave;           // 1: wave w takes batches w, w+W, ...; 0: one contiguous range
 };
 
 // ------------------------------------------------------------ decoding
@@ -115,41 +115,106 @@ __device__ __forceinline__ double chunk_elem_f64(const u32x4& w, int e) {
     return __longlong_as_double((long long)b);
 }
 
-// ------------------------------------------------------------ shuffles
+// ------------------------------------------------------------ lane exchange
+//
+// One step of a transposed butterfly reduction at lane distance D (a power
+// of two below 64).  Each lane holds two partial sums A (row slot i) and B
+// (row slot i + H).  Lanes whose bit D is clear end with A(self) + A(partner),
+// lanes whose bit D is set with B(self) + B(partner), where the partner
+// differs in bit D (and possibly in lower bits, which no earlier step has
+// used).  D = 32 and 16 use gfx950's permlane swaps, which exchange both
+// halves in one instruction; D = 8, 4, 2, 1 use DPP row_mirror,
+// row_half_mirror and quad permutations.
+
+__device__ __forceinline__ unsigned dpp_mov(unsigned v, int ctrl) {
+    switch (ctrl) {
+    case 0x140: return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true);
+    case 0x141: return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);
+    case 0x4E: return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
+    default: return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
+    }
+}
+
+template <int D>
+constexpr int dpp_ctrl() {
+    return D == 8 ? 0x140 : D == 4 ? 0x141 : D == 2 ? 0x4E : 0xB1;
+}
+
+// 32-bit words: returns the partner's copy of the half this lane keeps,
+// plus this lane's kept word (both as raw bits).
+template <int D>
+__device__ __forceinline__ void xchg_u32(unsigned a, unsigned b, bool up, unsigned& keep,
+                                         unsigned& got) {
+    if constexpr (D == 32 || D == 16) {
+        const u32x2 r = D == 32 ? __builtin_amdgcn_permlane32_swap(a, b, false, false)
+                                : __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        keep = r.x;   // lanes with bit clear: own A; set: partner's B
+        got = r.y;    // lanes with bit clear: partner's A; set: own B
+    } else {
+        const unsigned send = up ? a : b;
+        keep = up ? b : a;
+        got = dpp_mov(send, dpp_ctrl<D>());
+    }
+}
+
+template <int D>
+__device__ __forceinline__ float xstep(float a, float b, bool up) {
+    unsigned k, g;
+    xchg_u32<D>(__float_as_uint(a), __float_as_uint(b), up, k, g);
+    return __uint_as_float(k) + __uint_as_float(g);
+}
+
+template <int D>
+__device__ __forceinline__ double xstep(double a, double b, bool up) {
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    unsigned k0, g0, k1, g1;
+    xchg_u32<D>((unsigned)ua, (unsigned)ub, up, k0, g0);
+    xchg_u32<D>((unsigned)(ua >> 32), (unsigned)(ub >> 32), up, k1, g1);
+    const double k = __longlong_as_double((long long)(((unsigned long long)k1 << 32) | k0));
+    const double g = __longlong_as_double((long long)(((unsigned long long)g1 << 32) | g0));
+    return k + g;
+}
 
 struct HiLo {
     float h, l;
 };
 
-__device__ __forceinline__ float shfl_x(float v, int m) { return __shfl_xor(v, m, 64); }
-__device__ __forceinline__ double shfl_x(double v, int m) { return __shfl_xor(v, m, 64); }
-__device__ __forceinline__ HiLo shfl_x(HiLo v, int m) {
-    return HiLo{__shfl_xor(v.h, m, 64), __shfl_xor(v.l, m, 64)};
+template <int D>
+__device__ __forceinline__ HiLo xstep(HiLo a, HiLo b, bool up) {
+    return HiLo{xstep<D>(a.h, b.h, up), xstep<D>(a.l, b.l, up)};
 }
-__device__ __forceinline__ HiLo operator+(HiLo a, HiLo b) { return HiLo{a.h + b.h, a.l + b.l}; }
 
-// Transposed butterfly reduction over the LPR lanes of a segment.  On entry
-// v[j] is this lane's partial of row slot j (j < CNT == R).  After the steps
-// with distance D = LPR/2 .. 1: if R >= LPR the lane holds the complete sums
-// of slots cl*(R/LPR) + i in v[i] (i < R/LPR); otherwise v[0] holds the sum
-// of slot cl / (LPR/R), replicated on LPR/R lanes.
+// Transposed reduction over the LPR lanes of a segment (LPR a power of two,
+// segments aligned).  On entry v[j] is this lane's partial of row slot j
+// (j < R).  Afterwards, if R >= LPR, v[i] (i < R/LPR) holds the complete sum
+// of slot cl*(R/LPR) + i; otherwise v[0] holds the sum of slot cl/(LPR/R),
+// replicated on LPR/R lanes.  cl is the lane index within its segment.
 template <int D, int CNT, int R, typename V>
 __device__ __forceinline__ void seg_reduce(V (&v)[R], int lane) {
     if constexpr (D >= 1) {
+        const bool up = (lane & D) != 0;
         if constexpr (CNT > 1) {
             constexpr int H = CNT / 2;
-            const bool up = (lane & D) != 0;
 #pragma unroll
-            for (int i = 0; i < H; ++i) {
-                const V send = up ? v[i] : v[i + H];
-                const V keep = up ? v[i + H] : v[i];
-                v[i] = keep + shfl_x(send, D);
-            }
+            for (int i = 0; i < H; ++i) v[i] = xstep<D>(v[i], v[i + H], up);
             seg_reduce<D / 2, H, R, V>(v, lane);
         } else {
-            v[0] = v[0] + shfl_x(v[0], D);
+            v[0] = xstep<D>(v[0], v[0], up);
             seg_reduce<D / 2, 1, R, V>(v, lane);
         }
+    }
+}
+
+// Sum over the lanes that share this lane's position within its segment of
+// D lanes (exact xor partners; runs once per launch).
+template <int D>
+__device__ __forceinline__ double cross_segment_sum(double v) {
+    if constexpr (D < 64) {
+        v += __shfl_xor(v, D, 64);
+        return cross_segment_sum<D * 2>(v);
+    } else {
+        return v;
     }
 }
 
@@ -239,6 +304,17 @@ __device__ __forceinline__ void merge_partials(const FgParams& p) {
 
 // ------------------------------------------------------------ main kernel
 
+// Buffer descriptor word 3 for raw (untyped) buffers on gfx9-class GPUs.
+constexpr int kRsrcWord3 = 0x00020000;
+// Cache policy of the streaming loads: nontemporal.
+constexpr int kLoadNT = 2;
+
+template <int R, int CPL, int OWN>
+struct Tile {
+    u32x4 x[R][CPL];
+    unsigned yb[OWN];
+};
+
 template <int DT, int LPR, int CPL, int R, int WPB>
 __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     constexpr int ES = ElemSize<DT>::v;
@@ -249,19 +325,23 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     constexpr bool F64 = DT == DT_F64;
     constexpr int OWN = R >= LPR ? R / LPR : 1;   // rows owned per lane after the reduction
     constexpr int REP = R >= LPR ? 1 : LPR / R;   // lanes sharing one owned row
+    using rtype = typename std::conditional<F64, double, float>::type;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int seg = lane / LPR;
     const int cl = lane % LPR;
     const int NC = p.K / VE;
+    const uint32_t ldb = (uint32_t)(p.ldx * ES);   // row stride in bytes
 
     // ---- this lane's slice of beta (scale folded in for FP8) ----
     float bh[CPL][VE], bl[CPL][VE];
     double bd[CPL][VE];
+    uint32_t loff[CPL];   // byte offset of this lane's chunk i in row slot 0
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
         const int c = cl + i * LPR;
+        loff[i] = c < NC ? (uint32_t)seg * ldb + (uint32_t)c * 16u : 0x80000000u;
 #pragma unroll
         for (int e = 0; e < VE; ++e) {
             double b = 0.0;
@@ -278,6 +358,14 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
             }
         }
     }
+    // y offsets (within a batch) of the rows this lane owns after the reduction
+    uint32_t yoff[OWN];
+#pragma unroll
+    for (int o = 0; o < OWN; ++o) {
+        const int j = R >= LPR ? cl * OWN + o : cl / REP;
+        yoff[o] = (uint32_t)(j * RPW + seg);
+    }
+    const bool unique = R >= LPR || (cl % REP) == 0;
 
     double g64[CPL][VE];
 #pragma unroll
@@ -286,57 +374,54 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
         for (int e = 0; e < VE; ++e) g64[i][e] = 0.0;
     double facc = 0.0;
 
-    using rtype = typename std::conditional<F64, double, float>::type;
     __shared__ rtype rbuf[WPB][RPW][R];
 
-    const int64_t r0 = (int64_t)blockIdx.x * p.rows_per_block;
-    const int64_t r1 = min(p.N, r0 + p.rows_per_block);
-    const int64_t ldb = p.ldx * ES;   // row stride in bytes
+    // This wave's batches: first, first + step, ... below last.  Either
+    // grid-strided (all waves sweep memory together) or one contiguous,
+    // balanced range per wave.
+    const int64_t nbatch = (p.N + BATCH - 1) / BATCH;
+    const int64_t tw = (int64_t)gridDim.x * WPB;
+    const int64_t gw = (int64_t)blockIdx.x * WPB + wave;
+    const int64_t bfirst = p.interleave ? gw : nbatch * gw / tw;
+    const int64_t bstep = p.interleave ? tw : 1;
+    const int64_t blast = p.interleave ? nbatch : nbatch * (gw + 1) / tw;
 
-    for (int64_t base = r0 + (int64_t)wave * BATCH; base < r1; base += (int64_t)WPB * BATCH) {
-        // ---- 1. loads ----
-        u32x4 x[R][CPL];
+    auto load = [&](Tile<R, CPL, OWN>& t, int64_t b) {
+        const int64_t row0 = b * BATCH;
+        const int64_t nvalid = min((int64_t)BATCH, p.N - row0);
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(p.X + row0 * (int64_t)ldb), 0, (int)(nvalid * ldb), kRsrcWord3);
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int64_t row = base + j * RPW + seg;
-            const bool rv = row < r1;
+        for (int j = 0; j < R; ++j)
 #pragma unroll
-            for (int i = 0; i < CPL; ++i) {
-                const int c = cl + i * LPR;
-                if (rv && c < NC) {
-                    x[j][i] = __builtin_nontemporal_load(
-                        reinterpret_cast<const u32x4*>(p.X + row * ldb + (int64_t)c * 16));
-                } else {
-                    x[j][i] = u32x4{0u, 0u, 0u, 0u};
-                }
-            }
-        }
-        // y bytes of the rows this lane will own after the reduction
-        double yo[OWN];
-        int64_t rowo[OWN];
+            for (int i = 0; i < CPL; ++i)
+                t.x[j][i] = __builtin_amdgcn_raw_buffer_load_b128(
+                    rx, loff[i] + (uint32_t)(j * RPW) * ldb, 0, kLoadNT);
+        const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(p.y + row0), 0, (int)nvalid, kRsrcWord3);
 #pragma unroll
-        for (int i = 0; i < OWN; ++i) {
-            const int j = R >= LPR ? cl * OWN + i : cl / REP;
-            rowo[i] = base + j * RPW + seg;
-            yo[i] = rowo[i] < r1 ? (double)p.y[rowo[i]] : 0.0;
-        }
+        for (int o = 0; o < OWN; ++o) t.yb[o] = __builtin_amdgcn_raw_buffer_load_b8(ry, yoff[o], 0, kLoadNT);
+    };
 
-        // ---- 2+3. partial dots and transposed segment reduction ----
+    auto compute = [&](const Tile<R, CPL, OWN>& t, int64_t b) {
+        const int64_t row0 = b * BATCH;
+        const uint32_t nvalid = (uint32_t)min((int64_t)BATCH, p.N - row0);
+        // partial dot products and the transposed reduction
         double uo[OWN];
         if constexpr (F64) {
             double v[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                double s = 0.0;
+                double sacc = 0.0;
 #pragma unroll
                 for (int i = 0; i < CPL; ++i)
 #pragma unroll
-                    for (int e = 0; e < VE; ++e) s = fma(chunk_elem_f64(x[j][i], e), bd[i][e], s);
-                v[j] = s;
+                    for (int e = 0; e < VE; ++e) sacc = fma(chunk_elem_f64(t.x[j][i], e), bd[i][e], sacc);
+                v[j] = sacc;
             }
             seg_reduce<LPR / 2, R, R, double>(v, lane);
 #pragma unroll
-            for (int i = 0; i < OWN; ++i) uo[i] = v[i];
+            for (int o = 0; o < OWN; ++o) uo[o] = v[o];
         } else {
             HiLo v[R];
 #pragma unroll
@@ -345,7 +430,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
 #pragma unroll
                 for (int i = 0; i < CPL; ++i) {
                     float xv[VE];
-                    decode_chunk<DT>(x[j][i], xv);
+                    decode_chunk<DT>(t.x[j][i], xv);
 #pragma unroll
                     for (int e = 0; e < VE; ++e) {
                         sh = fmaf(xv[e], bh[i][e], sh);
@@ -356,38 +441,34 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
             }
             seg_reduce<LPR / 2, R, R, HiLo>(v, lane);
 #pragma unroll
-            for (int i = 0; i < OWN; ++i) uo[i] = (double)v[i].h + (double)v[i].l;
+            for (int o = 0; o < OWN; ++o) uo[o] = (double)v[o].h + (double)v[o].l;
         }
-
-        // ---- TR map on owned rows; r broadcast through LDS ----
-        const bool unique = R >= LPR || (cl % REP) == 0;
+        // TR map on owned rows (FP64); r to the segment through LDS
 #pragma unroll
-        for (int i = 0; i < OWN; ++i) {
-            double t, r;
-            tr_map(uo[i], yo[i], t, r);
-            const bool ok = rowo[i] < r1;
-            if (ok && unique) facc += t;
+        for (int o = 0; o < OWN; ++o) {
+            double tt, rr;
+            tr_map(uo[o], (double)(t.yb[o] & 1u), tt, rr);
+            const bool ok = yoff[o] < nvalid;
+            if (ok && unique) facc += tt;
             if (unique) {
-                const int j = R >= LPR ? cl * OWN + i : cl / REP;
-                rbuf[wave][seg][j] = ok ? (rtype)r : (rtype)0;
+                const int j = R >= LPR ? cl * OWN + o : cl / REP;
+                rbuf[wave][seg][j] = ok ? (rtype)rr : (rtype)0;
             }
         }
         __builtin_amdgcn_wave_barrier();
-        rtype rr[R];
+        rtype rs[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) rr[j] = rbuf[wave][seg][j];
+        for (int j = 0; j < R; ++j) rs[j] = rbuf[wave][seg][j];
         __builtin_amdgcn_wave_barrier();
-
-        // ---- 4. gradient contribution from the same registers ----
+        // gradient contribution from the same registers
         if constexpr (F64) {
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const double rj = rr[j];
+            for (int j = 0; j < R; ++j)
 #pragma unroll
                 for (int i = 0; i < CPL; ++i)
 #pragma unroll
-                    for (int e = 0; e < VE; ++e) g64[i][e] = fma(rj, chunk_elem_f64(x[j][i], e), g64[i][e]);
-            }
+                    for (int e = 0; e < VE; ++e)
+                        g64[i][e] = fma(rs[j], chunk_elem_f64(t.x[j][i], e), g64[i][e]);
         } else {
             float g32[CPL][VE];
 #pragma unroll
@@ -395,31 +476,39 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
 #pragma unroll
                 for (int e = 0; e < VE; ++e) g32[i][e] = 0.0f;
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
+            for (int j = 0; j < R; ++j)
 #pragma unroll
                 for (int i = 0; i < CPL; ++i) {
                     float xv[VE];
-                    decode_chunk<DT>(x[j][i], xv);
+                    decode_chunk<DT>(t.x[j][i], xv);
 #pragma unroll
-                    for (int e = 0; e < VE; ++e) g32[i][e] = fmaf(rr[j], xv[e], g32[i][e]);
+                    for (int e = 0; e < VE; ++e) g32[i][e] = fmaf(rs[j], xv[e], g32[i][e]);
                 }
-            }
 #pragma unroll
             for (int i = 0; i < CPL; ++i)
 #pragma unroll
                 for (int e = 0; e < VE; ++e) g64[i][e] += (double)g32[i][e];
         }
+    };
+
+    // two tiles in flight: the loads of batch b+1 overlap the math of batch b
+    Tile<R, CPL, OWN> ta, tb;
+    if (bfirst < blast) load(ta, bfirst);
+    for (int64_t b = bfirst; b < blast; b += 2 * bstep) {
+        if (b + bstep < blast) load(tb, b + bstep);
+        compute(ta, b);
+        if (b + bstep >= blast) break;
+        if (b + 2 * bstep < blast) load(ta, b + 2 * bstep);
+        compute(tb, b + bstep);
     }
 
     // ---- block merge: segments of a wave, then waves in LDS ----
 #pragma unroll
-    for (int d = LPR; d < 64; d <<= 1)
+    for (int i = 0; i < CPL; ++i)
 #pragma unroll
-        for (int i = 0; i < CPL; ++i)
+        for (int e = 0; e < VE; ++e) g64[i][e] = cross_segment_sum<LPR>(g64[i][e]);
 #pragma unroll
-            for (int e = 0; e < VE; ++e) g64[i][e] += shfl_x(g64[i][e], d);
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) facc += shfl_x(facc, d);
+    for (int d = 32; d >= 1; d >>= 1) facc += __shfl_xor(facc, d, 64);
 
     // Waves add their slices into one LDS vector in wave order.
     __shared__ double gsh[KT];
@@ -439,15 +528,15 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     }
     double* part = p.partials + (int64_t)blockIdx.x * (p.K + 1);
     for (int k = threadIdx.x; k < p.K; k += blockDim.x) {
-        double s = gsh[k];
-        if constexpr (DT == DT_FP8) s *= (double)p.scale[k];
-        part[1 + k] = s;
+        double sacc = gsh[k];
+        if constexpr (DT == DT_FP8) sacc *= (double)p.scale[k];
+        part[1 + k] = sacc;
     }
     if (threadIdx.x == 0) {
-        double s = 0.0;
+        double sacc = 0.0;
 #pragma unroll
-        for (int w = 0; w < WPB; ++w) s += fsh[w];
-        part[0] = s;
+        for (int w = 0; w < WPB; ++w) sacc += fsh[w];
+        part[0] = sacc;
     }
     merge_partials<WPB * 64>(p);
 }

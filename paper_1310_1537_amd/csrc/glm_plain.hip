@@ -1,5 +1,6 @@
 // Plain entry points: one data set, one beta per launch.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "fg_kernel.hpp"
@@ -72,6 +73,9 @@ glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
                  "plan: rows must be whole 16-byte chunks (K*%d and ldx*%d multiples of 16, X "
                  "16-byte aligned)",
                  es, es);
+    if (d.ldx * es > (1 << 21))
+        GLM_FAIL(GLM_EINVAL, "plan: row stride ldx*%d = %lld bytes exceeds 2 MiB", es,
+                 (long long)(d.ldx * es));
     const int nc = d.K / ve;
     Plan p;
     p.kind = 0;
@@ -83,16 +87,16 @@ glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
     p.fn = in.fn;
     p.rows_per_lane = in.R;
     p.wpb = WPB;
+    // Persistent grid: every wave streams one contiguous range of row batches.
     const int64_t wave_rows = (int64_t)in.R * (64 / p.lpr);
-    const int64_t block_rows = wave_rows * p.wpb;
-    const int64_t target = (int64_t)ctx->num_cu * 4;
-    int64_t nb = (d.N + block_rows - 1) / block_rows;
-    nb = std::max<int64_t>(1, std::min(nb, target));
-    int64_t rpb = (d.N + nb - 1) / nb;
-    rpb = (rpb + block_rows - 1) / block_rows * block_rows;
-    if (d.N == 0) rpb = 0;
-    p.rows_per_block = rpb;
-    p.nblocks = rpb ? (int)((d.N + rpb - 1) / rpb) : 1;
+    const int64_t nbatch = (d.N + wave_rows - 1) / wave_rows;
+    int bpc = 1;
+    if (const char* e = std::getenv("GLM_BLOCKS_PER_CU")) bpc = std::max(1, std::atoi(e));
+    const int64_t target = (int64_t)ctx->num_cu * bpc;
+    const int64_t need = (nbatch + p.wpb - 1) / p.wpb;
+    p.nblocks = (int)std::max<int64_t>(1, std::min(need, target));
+    p.interleave = 1;
+    if (const char* e = std::getenv("GLM_INTERLEAVE")) p.interleave = std::atoi(e) != 0;
     p.group = std::max(1, (int)std::ceil(std::sqrt((double)p.nblocks)));
     *plan = p;
     return GLM_OK;
@@ -123,7 +127,7 @@ static glm_status launch_plain(glm_ctx* ctx, const Dataset& ds, const double* be
     p.counters = s->counters;
     p.nblocks = pl.nblocks;
     p.group = pl.group;
-    p.rows_per_block = pl.rows_per_block;
+    p.interleave = pl.interleave;
     void* args[] = {&p};
     GLM_HIP_CHECK(hipLaunchKernel(pl.fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0,
                                   (hipStream_t)stream));

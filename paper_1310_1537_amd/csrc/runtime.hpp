@@ -58,7 +58,7 @@ struct Plan {
     int wpb = 4;           // waves per block
     int nblocks = 1;
     int group = 32;        // blocks per merge group
-    int64_t rows_per_block = 0;
+    int interleave = 1;    // grid-strided batches (1) or contiguous ranges (0)
     const void* fn = nullptr;   // __global__ function
 };
 
