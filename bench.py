@@ -67,20 +67,38 @@ def cpu_baseline(w, n_max: int, budget_s: float = 15.0):
     return res, dt
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--latency-calls", type=int, default=200)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the row-sharded design is described, not built). Run with --gpus 1.",
-              file=sys.stderr)
-        return 2
+def _timed_evals(glm, lib, ctx, ds, prior, betas, outs, K, warmup, steps, stream):
+    """warmup + steps sequential evaluations; returns (wall s, per-launch ms)."""
+    import ctypes
+    import numpy as np
+    import torch
+    pr = ctypes.byref(prior)
+    sp = stream.cuda_stream
+    bptr, optr = betas.data_ptr(), outs.data_ptr()
+    nb = betas.shape[0]
 
+    def launch(i):
+        st = lib.glm_logpost_grad(ctx, ds, bptr + (i % nb) * K * 8, pr,
+                                  optr + (i % nb) * (K + 1) * 8, sp)
+        if st:
+            raise glm.GlmError(st, glm.glm_last_error())
+
+    for i in range(warmup):
+        launch(i)
+    torch.cuda.synchronize()
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for j in range(steps):
+        ev0[j].record(stream)
+        launch(warmup + j)
+        ev1[j].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+
+
+def bench_plain_big(args):
     import numpy as np
     import torch
 
@@ -103,35 +121,8 @@ def main() -> int:
     ctx = glm.glm_create(0)
     ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
     prior = glm.make_prior(w.prec)
-    lib = glm.lib()
-    import ctypes
-    pr = ctypes.byref(prior)
-    sp = stream.cuda_stream
-    bptr = betas.data_ptr()
-    optr = outs.data_ptr()
-
-    def launch(i):
-        st = lib.glm_logpost_grad(ctx, ds, bptr + i * K * 8, pr, optr + i * (K + 1) * 8, sp)
-        if st:
-            raise glm.GlmError(st, glm.glm_last_error())
-
-    for i in range(args.warmup):
-        launch(i)
-    torch.cuda.synchronize()
-
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for j in range(args.steps):
-        i = args.warmup + j
-        ev0[j].record(stream)
-        launch(i)
-        ev1[j].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    kern_ms = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    wall, kern_ms = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K, args.warmup,
+                                 args.steps, stream)
     avg_ms = float(kern_ms.mean())
     print(f"[bench] {args.steps} evals in {wall:.3f} s; launch avg {avg_ms * 1e3:.1f} us",
           file=sys.stderr, flush=True)
@@ -189,6 +180,222 @@ def main() -> int:
                                             f"N={N} K={K} workload, single-threaded FP64 C"}
     glm.glm_dataset_unregister(ctx, ds)
     glm.glm_destroy(ctx)
+    return result
+
+
+def bench_precision(args):
+    """N=8,000,000, K=512: the same trajectory on FP32, BF16 and FP8-E4M3
+    (per-column FP32 scales) copies of X; throughput and error per format."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    N = args.n or 8_000_000
+    K = 512
+    w = synth.plain_big(N=N, K=K, n_evals=1000, workload_index=2)
+    print(f"[bench] precision workload N={N} K={K} generated", file=sys.stderr, flush=True)
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    ctx = glm.glm_create(0)
+    Xb = torch.empty((N, K), dtype=torch.uint16, device=dev)
+    glm.glm_quantize_bf16(ctx, X, Xb)
+    sc = torch.empty(K, dtype=torch.float32, device=dev)
+    glm.glm_fp8_col_scales(ctx, X, sc)
+    Xq = torch.empty((N, K), dtype=torch.uint8, device=dev)
+    glm.glm_quantize_fp8(ctx, X, sc, Xq)
+    torch.cuda.synchronize()
+    total = args.warmup + args.steps
+    idx = np.arange(total) % 1000
+    betas = torch.from_numpy(np.ascontiguousarray(w.betas[idx])).to(dev)
+    stream = torch.cuda.current_stream()
+    prior = glm.make_prior(w.prec)
+    formats = {}
+    for name, Xs, dt, scale, es in (("fp32", X, glm.GLM_F32, None, 4),
+                                    ("bf16", Xb, glm.GLM_BF16, None, 2),
+                                    ("fp8", Xq, glm.GLM_FP8_E4M3, sc, 1)):
+        ds = glm.glm_dataset_register(ctx, glm.make_desc(Xs, y, dtype=dt, col_scale=scale))
+        outs = torch.empty((total, K + 1), dtype=torch.float64, device=dev)
+        wall, kern_ms = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K,
+                                     args.warmup, args.steps, stream)
+        bytes_alg = float(N) * K * es + N
+        avg = float(kern_ms.mean())
+        formats[name] = {"evals_per_s": args.steps / wall, "launch_us_avg": avg * 1e3,
+                         "GBps": bytes_alg / (avg * 1e-3) / 1e9,
+                         "frac_peak": bytes_alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+                         "bytes_per_launch": bytes_alg, "first_out": outs[0].cpu().numpy()}
+        glm.glm_dataset_unregister(ctx, ds)
+        print(f"[bench] {name}: {formats[name]['evals_per_s']:.1f} evals/s "
+              f"{formats[name]['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        import oracle
+        b0 = w.betas[0]
+        t0 = time.perf_counter()
+        f32o = oracle.logpost_grad(w.X, w.y, b0, w.prec)
+        dt_cpu = time.perf_counter() - t0
+        qb = Xb.cpu().numpy()
+        bfo = oracle.logpost_grad(qb, w.y, b0, w.prec, dtype="bf16")
+        del qb
+        qq, scn = Xq.cpu().numpy(), sc.cpu().numpy()
+        f8o = oracle.logpost_grad(qq, w.y, b0, w.prec, dtype="fp8", scale=scn)
+        del qq
+
+        def err(out, ref):
+            return {"f_rel": abs(out[0] - ref[0]) / abs(ref[0]),
+                    "g_rel_norm": float(np.linalg.norm(out[1:] - ref[1]) / np.linalg.norm(ref[1]))}
+        formats["fp32"]["kernel_err"] = err(formats["fp32"]["first_out"], f32o)
+        formats["bf16"]["kernel_err"] = err(formats["bf16"]["first_out"], bfo)
+        formats["bf16"]["storage_err"] = err(formats["bf16"]["first_out"], f32o)
+        formats["fp8"]["kernel_err"] = err(formats["fp8"]["first_out"], f8o)
+        formats["fp8"]["storage_err"] = err(formats["fp8"]["first_out"], f32o)
+    for f in formats.values():
+        f.pop("first_out")
+    glm.glm_destroy(ctx)
+    b = formats["bf16"]
+    result = {
+        "metric": "logpost+grad evals/s (fused f+g, FP64 result) & HBM GB/s % peak",
+        "value": b["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 / b["evals_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"precision: N={N} K={K}, X as FP32 / BF16 / FP8-E4M3 "
+                               "(per-column scales), same trajectory", "N": N, "K": K},
+        "roofline": {"bound": "hbm", "achieved": b["GBps"], "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": b["frac_peak"], "traffic": None},
+        "formats": formats,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = {"value": 1.0 / dt_cpu, "unit": "evals/s", "cores": 1,
+                                  "kind": "oracle", "sample": "one FP32 evaluation at the "
+                                  "first trajectory point, single-threaded FP64 C"}
+    return result
+
+
+def bench_batched(args):
+    """Hierarchical model: 2,000 groups (sizes LogNormal(ln 500, 1.2) clipped
+    to [20, 50,000]), K = 32, FP32; each step evaluates every group at its
+    current beta_g in one launch, the betas following per-group random walks.
+    Compared with one plain launch per group."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    w = synth.hierarchical()
+    G, K = w.betas.shape
+    N = int(w.offsets[-1])
+    steps = args.steps
+    inc = synth.hierarchical_steps(G, K, min(steps + args.warmup, 500))
+    traj = w.betas[None] + np.cumsum(inc, axis=0)
+    nt = traj.shape[0]
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    B = torch.from_numpy(np.ascontiguousarray(traj)).to(dev)
+    mu = torch.from_numpy(w.mu).to(dev)
+    out = torch.empty((nt, G, K + 1), dtype=torch.float64, device=dev)
+    ctx = glm.glm_create(0)
+    desc = glm.make_desc(X, y)
+    t0 = time.perf_counter()
+    gs = glm.glm_groupset_create(ctx, desc, w.offsets, tune=True)
+    t_create = time.perf_counter() - t0
+    info = glm.glm_groupset_query(gs)
+    prior = glm.make_prior(w.prec, mu)
+    lib = glm.lib()
+    pr = ctypes.byref(prior)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    def launch(i):
+        st = lib.glm_logpost_grad_batched(ctx, gs, B.data_ptr() + (i % nt) * G * K * 8, pr,
+                                          out.data_ptr() + (i % nt) * G * (K + 1) * 8, sp)
+        if st:
+            raise glm.GlmError(st, glm.glm_last_error())
+
+    for i in range(args.warmup):
+        launch(i)
+    torch.cuda.synchronize()
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for j in range(steps):
+        ev0[j].record(stream)
+        launch(args.warmup + j)
+        ev1[j].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    bytes_alg = float(N) * K * 4 + N
+    avg = float(kern_ms.mean())
+
+    # one plain launch per group, same betas (a few steps)
+    ids = [glm.glm_dataset_register(ctx, glm.make_desc(X[w.offsets[g]:w.offsets[g + 1]],
+                                                       y[w.offsets[g]:w.offsets[g + 1]]))
+           for g in range(G)]
+    outp = torch.empty((G, K + 1), dtype=torch.float64, device=dev)
+    psteps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(psteps):
+        base = B.data_ptr() + (j % nt) * G * K * 8
+        for g in range(G):
+            st = lib.glm_logpost_grad(ctx, ids[g], base + g * K * 8, pr,
+                                      outp.data_ptr() + g * (K + 1) * 8, sp)
+            if st:
+                raise glm.GlmError(st, glm.glm_last_error())
+    torch.cuda.synchronize()
+    wall_plain = (time.perf_counter() - t0) / psteps
+    for i in ids:
+        glm.glm_dataset_unregister(ctx, i)
+
+    result = {
+        "metric": "logpost+grad evals/s (fused f+g, FP64 result) & HBM GB/s % peak",
+        "value": steps / wall, "unit": "steps/s (all 2000 groups per step)", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"hierarchical: G={G} groups, N={N} rows, K={K}, FP32",
+                   "G": G, "N": N, "K": K},
+        "group_evals_per_s": G * steps / wall,
+        "roofline": {"bound": "hbm", "achieved": bytes_alg / (avg * 1e-3) / 1e9,
+                     "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": bytes_alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, "traffic": None,
+                     "bytes_per_launch": bytes_alg, "launch_us_avg": avg * 1e3,
+                     "note": "X is 263 MB, about the 256 MB Infinity Cache: repeated steps "
+                             "may be served partly from it"},
+        "schedule": info, "groupset_create_s": t_create,
+        "plain_per_group": {"ms_per_step": wall_plain * 1e3,
+                            "speedup_of_batched": wall_plain / (wall / steps)},
+    }
+    glm.glm_groupset_destroy(gs)
+    glm.glm_destroy(ctx)
+    return result
+
+
+WORKLOADS = {"plain_big": bench_plain_big, "precision": bench_precision,
+             "batched": bench_batched}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="plain_big", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=0, help="override N (precision workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-calls", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the row-sharded design is described, not built). Run with --gpus 1.",
+              file=sys.stderr)
+        return 2
+    result = WORKLOADS[args.workload](args)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -162,6 +162,55 @@ glm_status glm_logpost_grad_host(glm_ctx* ctx, glm_dataset_id id,
                                  const double* beta_host, const glm_prior* prior,
                                  double* f, double* g_host);
 
+/* ------------------------------------------------------- batched (groups) */
+
+/* Hierarchical model (Sec. 4.1): G groups, each with its own rows of one
+ * stacked data set and its own coefficient vector beta_g; group g's
+ * log-likelihood is the plain one over rows offsets[g] .. offsets[g+1]-1.
+ * The groups are conditionally independent given the shared prior
+ * parameters (Sec. 2.3, Theorem 2.1), so one launch evaluates all of them. */
+typedef struct glm_groupset glm_groupset;
+
+typedef struct {
+    int64_t tile_rows;   /* groups longer than this are split into tiles        */
+    int32_t blocks;      /* grid size of the persistent launch                   */
+    int32_t waves;       /* waves that share the static work schedule            */
+    int32_t items;       /* scheduled work items (whole groups + tiles)          */
+    int32_t split_tiles; /* tiles of split groups (partials merged in-kernel)    */
+    double tuned_us;     /* measured time of the chosen shape (0 if not tuned)   */
+} glm_groupset_info;
+
+/* Builds the static schedule of a group set.  concat describes the stacked
+ * data (same rules as glm_dataset_register; the caller owns the buffers and
+ * keeps them alive until the group set is destroyed).  offsets_host: G + 1
+ * host int64, offsets[0] = 0, non-decreasing, offsets[G] = concat->N (empty
+ * groups allowed: their result is the prior alone).  tune != 0 times the
+ * candidate tile lengths and grid sizes on this group set at beta = 0 and
+ * keeps the fastest (the choice is cached per shape for the process, and in
+ * the file named by GLM_TUNE_CACHE if set); tune == 0 uses the default.
+ * Synchronises the device.  Errors: GLM_EINVAL, GLM_EDTYPE, GLM_ENOMEM,
+ * GLM_EHIP. */
+glm_status glm_groupset_create(glm_ctx* ctx, const glm_dataset_desc* concat,
+                               const int64_t* offsets_host, int32_t G, int32_t tune,
+                               glm_groupset** out);
+
+/* Frees the group set's device memory after synchronising the device. */
+glm_status glm_groupset_destroy(glm_groupset* gs);
+
+/* Shape of the schedule in use. */
+glm_status glm_groupset_query(const glm_groupset* gs, glm_groupset_info* info);
+
+/* f_g and g_g for every group in one launch.
+ *   betas  device, G x K doubles (row g = beta_g)
+ *   prior  host struct: prec, and mean = NULL (zero), K doubles (shared) or,
+ *          with mean_per_group != 0, G x K doubles (device)
+ *   out    device, G x (1 + K) doubles: row g = [f_g, g_g]
+ * Calls on one group set share its scratch (tile partials and tickets), so
+ * they must be ordered: issue them on one stream.  Errors: GLM_EINVAL,
+ * GLM_EHIP. */
+glm_status glm_logpost_grad_batched(glm_ctx* ctx, glm_groupset* gs, const double* betas,
+                                    const glm_prior* prior, double* out, void* stream);
+
 /* ----------------------------------------------------- storage conversions */
 
 /* BF16 copy of an FP32 matrix, round to nearest even (NaN stays NaN).

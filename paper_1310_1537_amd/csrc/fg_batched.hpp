@@ -1,0 +1,218 @@
+// Batched evaluation for the hierarchical model (Sec. 4.1): G groups, each
+// with its own rows of the stacked X / y and its own coefficient vector,
+// evaluated in one launch.
+//
+// The host splits groups larger than T rows into near-equal tiles and
+// assigns the resulting work items to waves ahead of time by a size proxy
+// (longest processing time first), the static pre-allocation the paper
+// proposes for uneven groups (Sec. 4.1).  A wave streams each of its items
+// with the same tile machinery as the plain kernel.  An item that is a whole
+// group is finished by its wave (no cross-wave traffic at all); the tiles of
+// a split group write partials, and the last tile to finish (atomic ticket
+// per group) adds them in tile order and applies the group's prior.
+#pragma once
+
+#include "fg_kernel.hpp"
+
+namespace glmk {
+
+struct BatchItem {
+    int64_t r0, r1;   // rows [r0, r1) of the stacked matrix
+    int32_t group;
+    int32_t tile;     // -1: the whole group; else partial slot index
+};
+
+struct BatchedParams {
+    const unsigned char* X;
+    int64_t ldx;
+    const uint8_t* y;
+    int K;
+    const float* scale;          // FP8 column scales
+    const double* betas;         // G x K
+    const double* mean;          // nullptr, K, or G x K (mean_per_group)
+    int mean_per_group;
+    double prec;
+    double* out;                 // G x (1 + K)
+    const BatchItem* items;
+    const int32_t* wave_items;   // total_waves + 1 offsets into items
+    const int32_t* tile_first;   // per group: first partial slot (split groups)
+    const int32_t* tile_count;   // per group: number of tiles (0 = not split)
+    const int32_t* block_groups_ptr;   // nblocks + 1 offsets into block_groups
+    const int32_t* block_groups;       // split groups each block holds tiles of
+    const int32_t* group_blocks;       // per group: number of distinct blocks holding its tiles
+    double* partials;            // ntiles x (1 + K)
+    unsigned* counters;          // G tickets, zero between launches
+};
+
+template <int DT, int LPR, int CPL, int R, int WPB>
+__global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
+    using WT = WaveTile<DT, LPR, CPL, R>;
+    using Tile = typename WT::Tile;
+    constexpr int VE = WT::VE;
+    constexpr int NT = WPB * 64;
+    constexpr int BATCH = WT::BATCH;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gw = blockIdx.x * WPB + wave;
+    const int K = p.K;
+    const int K1 = K + 1;
+
+    WT wt;
+    wt.init(threadIdx.x & 63, K, p.ldx);
+    __shared__ typename WT::rtype rbuf[WPB][WT::RPW * R];
+
+    // The wave's items are streamed as one sequence of batches, so the next
+    // batch is prefetched across item boundaries too; every item yields at
+    // least one batch (an empty group one empty batch).  Queue state and
+    // batch descriptors are wave-uniform (scalar registers).
+    const int it0 = p.wave_items[gw];
+    const int it1 = p.wave_items[gw + 1];
+    int qit = it0;                                   // item of the next batch to load
+    BatchItem qitem{0, 0, 0, -1};
+    if (qit < it1) qitem = p.items[qit];
+    int64_t qr = qitem.r0;                           // its first row
+
+    struct Meta {
+        int it;          // item index, it1 = none
+        int64_t row0, r1;
+        bool first, last;
+    };
+    auto next = [&]() {
+        Meta m;
+        m.it = qit;
+        m.row0 = qr;
+        m.r1 = qit < it1 ? qitem.r1 : 0;
+        m.first = qit < it1 && qr == qitem.r0;
+        m.last = qit < it1 && qr + BATCH >= qitem.r1;
+        if (qit < it1) {
+            if (qr + BATCH < qitem.r1) {
+                qr += BATCH;
+            } else {
+                ++qit;
+                if (qit < it1) {
+                    qitem = p.items[qit];
+                    qr = qitem.r0;
+                }
+            }
+        }
+        return m;
+    };
+
+    BatchItem citem{0, 0, 0, -1};   // item being computed
+    auto compute = [&](const Tile& t, const Meta& m) {
+        if (m.first) {
+            citem = p.items[m.it];
+            wt.set_beta(p.betas + (int64_t)citem.group * K, p.scale);
+            wt.zero_acc();
+        }
+        wt.compute(t, (uint32_t)max((int64_t)0, min((int64_t)BATCH, m.r1 - m.row0)), rbuf[wave]);
+        if (!m.last) return;
+        // item done: whole group -> its result; tile of a split group -> its partial
+        wt.wave_totals();
+        const int g = citem.group;
+        const double* beta = p.betas + (int64_t)g * K;
+        const double* mn = p.mean ? (p.mean_per_group ? p.mean + (int64_t)g * K : p.mean) : nullptr;
+        double* dst = citem.tile < 0 ? nullptr : p.partials + (int64_t)citem.tile * K1;
+        double* o = p.out + (int64_t)g * K1;
+        double pf = 0.0;
+        if (wt.seg == 0) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                for (int e = 0; e < VE; ++e)
+                    if (wt.col_ok(i)) {
+                        const int k = wt.col(i, e);
+                        double v = wt.g64[i][e];
+                        if constexpr (DT == DT_FP8) v *= (double)p.scale[k];
+                        if (dst) {
+                            dst[1 + k] = v;
+                        } else {
+                            const double d = beta[k] - (mn ? mn[k] : 0.0);
+                            pf += d * d;
+                            o[1 + k] = v - p.prec * d;
+                        }
+                    }
+        }
+        if (dst) {
+            if (wt.lane == 0) dst[0] = wt.facc;
+        } else {
+            for (int d = 1; d < LPR; d <<= 1) pf += __shfl_xor(pf, d, 64);
+            if (wt.lane == 0) o[0] = wt.facc - 0.5 * p.prec * pf;
+        }
+    };
+
+    Tile ta, tb;
+    Meta ma = next();
+    wt.load(ta, p.X, p.y, ma.row0, ma.r1 - ma.row0);
+    while (true) {
+        const Meta mb = next();
+        wt.load(tb, p.X, p.y, mb.row0, mb.r1 - mb.row0);
+        if (ma.it >= it1) break;
+        compute(ta, ma);
+        if (mb.it >= it1) break;
+        ma = next();
+        wt.load(ta, p.X, p.y, ma.row0, ma.r1 - ma.row0);
+        compute(tb, mb);
+    }
+
+    // Split groups: once every wave of this block is done, the block takes
+    // one ticket per split group it holds tiles of; the block completing a
+    // group's count adds that group's tile partials in tile order.  One
+    // release fence per block (not per tile) publishes the partials.
+    const int q0 = p.block_groups_ptr[blockIdx.x];
+    const int q1 = p.block_groups_ptr[blockIdx.x + 1];
+    if (q0 == q1) return;
+    // The barrier orders every wave's partial stores before wave 0's
+    // agent-scope release fence; the tickets themselves can then be relaxed.
+    __syncthreads();
+    if (wave == 0) __threadfence();
+    __shared__ unsigned s_win[NT];
+    for (int qb = q0; qb < q1; qb += NT) {
+        if (wave == 0) {
+            for (int qq = qb + wt.lane; qq < min(q1, qb + NT); qq += 64) {
+                const int g = p.block_groups[qq];
+                const unsigned prev = __hip_atomic_fetch_add(&p.counters[g], 1u, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                s_win[qq - qb] = prev == (unsigned)(p.group_blocks[g] - 1) ? 1u : 0u;
+            }
+            __threadfence();   // acquire side: tiles published by other blocks
+        }
+        __syncthreads();
+        const int nq = min(NT, q1 - qb);
+        for (int j = 0; j < nq; ++j) {
+            if (!s_win[j]) continue;
+            const int g = p.block_groups[qb + j];
+            const int t0 = p.tile_first[g];
+            const int nt = p.tile_count[g];
+            const double* beta = p.betas + (int64_t)g * K;
+            const double* m =
+                p.mean ? (p.mean_per_group ? p.mean + (int64_t)g * K : p.mean) : nullptr;
+            double* o = p.out + (int64_t)g * K1;
+            double pf = 0.0;
+            for (int k = threadIdx.x; k < K1; k += NT) {
+                const double sacc = ordered_sum(p.partials + (int64_t)t0 * K1 + k, nt, K1);
+                if (k == 0) {
+                    o[0] = sacc;
+                } else {
+                    const double d = beta[k - 1] - (m ? m[k - 1] : 0.0);
+                    pf += d * d;
+                    o[k] = sacc - p.prec * d;
+                }
+            }
+            __shared__ double s_pf[NT];
+            s_pf[threadIdx.x] = pf;
+            __syncthreads();
+            for (int w = NT / 2; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) s_pf[threadIdx.x] += s_pf[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                o[0] = o[0] - 0.5 * p.prec * s_pf[0];
+                __hip_atomic_store(&p.counters[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace glmk

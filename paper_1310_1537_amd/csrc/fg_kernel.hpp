@@ -232,6 +232,21 @@ __device__ __forceinline__ void tr_map(double u, double yv, double& t, double& r
 
 // ------------------------------------------------------------ finalisation
 
+// sum_{t < n} a[t * stride] in index order, with 16 loads in flight: the
+// loads of a block are independent, the additions keep the fixed order
+// (padding adds +0.0, which leaves any sum but -0.0 unchanged).
+__device__ __forceinline__ double ordered_sum(const double* a, int n, int64_t stride) {
+    double s = 0.0;
+    for (int t = 0; t < n; t += 16) {
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = t + j < n ? a[(int64_t)(t + j) * stride] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += v[j];
+    }
+    return s;
+}
+
 // Called by every thread of every block after the block has written its
 // partial (1 + K doubles at partials + blockIdx.x * (1 + K)).
 // NT is the block size (a power of two).
@@ -245,43 +260,39 @@ __device__ __forceinline__ void merge_partials(const FgParams& p) {
     const int b1 = min(p.nblocks, b0 + p.group);
     const int ngroups = (p.nblocks + p.group - 1) / p.group;
 
-    __threadfence();
+    // The barrier orders every wave's stores before thread 0's agent-scope
+    // release fence; the ticket itself can then be a relaxed atomic.
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(&p.counters[grp], 1u, __ATOMIC_ACQ_REL,
+        __threadfence();
+        const unsigned prev = __hip_atomic_fetch_add(&p.counters[grp], 1u, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == (unsigned)(b1 - b0 - 1)) ? 1u : 0u;
+        if (s_last) __threadfence();   // acquire side
     }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
 
-    for (int k = threadIdx.x; k < K1; k += blockDim.x) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int b = b0; b < b1; ++b) s += p.partials[(int64_t)b * K1 + k];
-        p.gpart[(int64_t)grp * K1 + k] = s;
-    }
+    for (int k = threadIdx.x; k < K1; k += blockDim.x)
+        p.gpart[(int64_t)grp * K1 + k] = ordered_sum(p.partials + (int64_t)b0 * K1 + k, b1 - b0, K1);
     if (threadIdx.x == 0)
         __hip_atomic_store(&p.counters[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(&p.counters[ngroups], 1u, __ATOMIC_ACQ_REL,
+        __threadfence();
+        const unsigned prev = __hip_atomic_fetch_add(&p.counters[ngroups], 1u, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == (unsigned)(ngroups - 1)) ? 1u : 0u;
+        if (s_last) __threadfence();
     }
     __syncthreads();
     if (!s_last) return;
-    __threadfence();
 
     // Final sums in group order, plus the Gaussian prior N(mean, prec^-1 I).
     double pf = 0.0;
     for (int k = threadIdx.x; k < K1; k += blockDim.x) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int g = 0; g < ngroups; ++g) s += p.gpart[(int64_t)g * K1 + k];
+        const double s = ordered_sum(p.gpart + k, ngroups, K1);
         if (k == 0) {
             p.out[0] = s;   // likelihood part; prior added below
         } else {
@@ -302,95 +313,129 @@ __device__ __forceinline__ void merge_partials(const FgParams& p) {
     }
 }
 
-// ------------------------------------------------------------ main kernel
+// ------------------------------------------------------------ wave tiles
 
 // Buffer descriptor word 3 for raw (untyped) buffers on gfx9-class GPUs.
 constexpr int kRsrcWord3 = 0x00020000;
 // Cache policy of the streaming loads: nontemporal.
 constexpr int kLoadNT = 2;
 
-template <int R, int CPL, int OWN>
-struct Tile {
-    u32x4 x[R][CPL];
-    unsigned yb[OWN];
-};
-
-template <int DT, int LPR, int CPL, int R, int WPB>
-__global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
-    constexpr int ES = ElemSize<DT>::v;
-    constexpr int VE = 16 / ES;            // elements per 16-byte chunk
-    constexpr int RPW = 64 / LPR;          // rows per wave-wide load
-    constexpr int BATCH = R * RPW;         // rows per wave per batch
-    constexpr int KT = LPR * CPL * VE;     // columns this instance can cover
-    constexpr bool F64 = DT == DT_F64;
-    constexpr int OWN = R >= LPR ? R / LPR : 1;   // rows owned per lane after the reduction
-    constexpr int REP = R >= LPR ? 1 : LPR / R;   // lanes sharing one owned row
+// The per-wave machinery shared by the plain and the batched kernels: one
+// wave streams batches of BATCH = R * RPW consecutive rows, each lane
+// holding R row slots of CPL 16-byte chunks, and accumulates f and its
+// columns of the gradient.
+template <int DT, int LPR, int CPL, int R>
+struct WaveTile {
+    static constexpr int ES = ElemSize<DT>::v;
+    static constexpr int LANES = LPR;             // lanes per row
+    static constexpr int CHUNKS = CPL;            // chunks per lane per row
+    static constexpr int VE = 16 / ES;            // elements per 16-byte chunk
+    static constexpr int RPW = 64 / LPR;          // rows per wave-wide load
+    static constexpr int BATCH = R * RPW;         // rows per batch
+    static constexpr int KT = LPR * CPL * VE;     // columns an instance covers
+    static constexpr bool F64 = DT == DT_F64;
+    static constexpr int OWN = R >= LPR ? R / LPR : 1;   // rows owned per lane after reduction
+    static constexpr int REP = R >= LPR ? 1 : LPR / R;   // lanes sharing one owned row
     using rtype = typename std::conditional<F64, double, float>::type;
 
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int seg = lane / LPR;
-    const int cl = lane % LPR;
-    const int NC = p.K / VE;
-    const uint32_t ldb = (uint32_t)(p.ldx * ES);   // row stride in bytes
+    struct Tile {
+        u32x4 x[R][CPL];
+        unsigned yb[OWN];
+    };
 
-    // ---- this lane's slice of beta (scale folded in for FP8) ----
-    float bh[CPL][VE], bl[CPL][VE];
-    double bd[CPL][VE];
-    uint32_t loff[CPL];   // byte offset of this lane's chunk i in row slot 0
+    int lane, seg, cl, NC;
+    uint32_t ldb;            // row stride in bytes
+    uint32_t loff[CPL];      // byte offset of this lane's chunk i in row slot 0
+    uint32_t yoff[OWN];      // row slot (within a batch) of each owned row
+    bool unique;             // this lane accounts its owned rows in f
+    float bh[CPL][VE], bl[CPL][VE];   // beta = bh + bl (FP32 storage kinds)
+    double bd[CPL][VE];               // beta (FP64 storage)
+    double g64[CPL][VE];              // this lane's gradient columns
+    double facc;
+
+    __device__ __forceinline__ void init(int lane_, int K, int64_t ldx) {
+        lane = lane_;
+        seg = lane / LPR;
+        cl = lane % LPR;
+        NC = K / VE;
+        ldb = (uint32_t)(ldx * ES);
 #pragma unroll
-    for (int i = 0; i < CPL; ++i) {
-        const int c = cl + i * LPR;
-        loff[i] = c < NC ? (uint32_t)seg * ldb + (uint32_t)c * 16u : 0x80000000u;
+        for (int i = 0; i < CPL; ++i) {
+            const int c = cl + i * LPR;
+            loff[i] = c < NC ? (uint32_t)seg * ldb + (uint32_t)c * 16u : 0x80000000u;
+        }
 #pragma unroll
-        for (int e = 0; e < VE; ++e) {
-            double b = 0.0;
-            if (c < NC) {
-                const int k = c * VE + e;
-                b = p.beta[k];
-                if constexpr (DT == DT_FP8) b *= (double)p.scale[k];
-            }
-            if constexpr (F64) {
-                bd[i][e] = b;
-            } else {
-                bh[i][e] = (float)b;
-                bl[i][e] = (float)(b - (double)bh[i][e]);
+        for (int o = 0; o < OWN; ++o) {
+            const int j = R >= LPR ? cl * OWN + o : cl / REP;
+            yoff[o] = (uint32_t)(j * RPW + seg);
+        }
+        unique = R >= LPR || (cl % REP) == 0;
+    }
+
+    // Column k of this lane's chunk i, element e.
+    __device__ __forceinline__ int col(int i, int e) const { return (cl + i * LPR) * VE + e; }
+    __device__ __forceinline__ bool col_ok(int i) const { return cl + i * LPR < NC; }
+
+    // beta (K doubles); FP8 folds the column scales into it.
+    __device__ __forceinline__ void set_beta(const double* beta, const float* scale) {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+                double b = 0.0;
+                if (col_ok(i)) {
+                    b = beta[col(i, e)];
+                    if constexpr (DT == DT_FP8) b *= (double)scale[col(i, e)];
+                }
+                if constexpr (F64) {
+                    bd[i][e] = b;
+                } else {
+                    bh[i][e] = (float)b;
+                    bl[i][e] = (float)(b - (double)bh[i][e]);
+                }
             }
         }
     }
-    // y offsets (within a batch) of the rows this lane owns after the reduction
-    uint32_t yoff[OWN];
+
+    // Same from this lane's beta values already in registers.
+    __device__ __forceinline__ void set_beta_values(const double (&b)[CPL][VE], const float* scale) {
 #pragma unroll
-    for (int o = 0; o < OWN; ++o) {
-        const int j = R >= LPR ? cl * OWN + o : cl / REP;
-        yoff[o] = (uint32_t)(j * RPW + seg);
+        for (int i = 0; i < CPL; ++i) {
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+                double v = b[i][e];
+                if constexpr (DT == DT_FP8) v *= col_ok(i) ? (double)scale[col(i, e)] : 0.0;
+                if constexpr (F64) {
+                    bd[i][e] = v;
+                } else {
+                    bh[i][e] = (float)v;
+                    bl[i][e] = (float)(v - (double)bh[i][e]);
+                }
+            }
+        }
     }
-    const bool unique = R >= LPR || (cl % REP) == 0;
 
-    double g64[CPL][VE];
+    __device__ __forceinline__ void zero_acc() {
 #pragma unroll
-    for (int i = 0; i < CPL; ++i)
+        for (int i = 0; i < CPL; ++i)
 #pragma unroll
-        for (int e = 0; e < VE; ++e) g64[i][e] = 0.0;
-    double facc = 0.0;
+            for (int e = 0; e < VE; ++e) g64[i][e] = 0.0;
+        facc = 0.0;
+    }
 
-    __shared__ rtype rbuf[WPB][RPW][R];
-
-    // This wave's batches: first, first + step, ... below last.  Either
-    // grid-strided (all waves sweep memory together) or one contiguous,
-    // balanced range per wave.
-    const int64_t nbatch = (p.N + BATCH - 1) / BATCH;
-    const int64_t tw = (int64_t)gridDim.x * WPB;
-    const int64_t gw = (int64_t)blockIdx.x * WPB + wave;
-    const int64_t bfirst = p.interleave ? gw : nbatch * gw / tw;
-    const int64_t bstep = p.interleave ? tw : 1;
-    const int64_t blast = p.interleave ? nbatch : nbatch * (gw + 1) / tw;
-
-    auto load = [&](Tile<R, CPL, OWN>& t, int64_t b) {
-        const int64_t row0 = b * BATCH;
-        const int64_t nvalid = min((int64_t)BATCH, p.N - row0);
+    // Loads the batch of rows row0 .. row0 + BATCH - 1 of a row block whose
+    // valid rows end at row0 + navail (navail <= 0: nothing valid).  Rows past
+    // the end come back as zeros from the buffer range check without touching
+    // memory, so the call never needs a branch.
+    __device__ __forceinline__ void load(Tile& t, const unsigned char* X, const uint8_t* y,
+                                         int64_t row0, int64_t navail) const {
+        int64_t nvalid = min((int64_t)BATCH, navail);
+        if (nvalid <= 0) {
+            nvalid = 0;
+            row0 = 0;
+        }
         const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(p.X + row0 * (int64_t)ldb), 0, (int)(nvalid * ldb), kRsrcWord3);
+            (void*)(X + row0 * (int64_t)ldb), 0, (int)(nvalid * ldb), kRsrcWord3);
 #pragma unroll
         for (int j = 0; j < R; ++j)
 #pragma unroll
@@ -398,14 +443,18 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
                 t.x[j][i] = __builtin_amdgcn_raw_buffer_load_b128(
                     rx, loff[i] + (uint32_t)(j * RPW) * ldb, 0, kLoadNT);
         const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
-            (void*)(p.y + row0), 0, (int)nvalid, kRsrcWord3);
+            (void*)(y + row0), 0, (int)nvalid, kRsrcWord3);
 #pragma unroll
-        for (int o = 0; o < OWN; ++o) t.yb[o] = __builtin_amdgcn_raw_buffer_load_b8(ry, yoff[o], 0, kLoadNT);
-    };
+        for (int o = 0; o < OWN; ++o)
+            t.yb[o] = __builtin_amdgcn_raw_buffer_load_b8(ry, yoff[o], 0, kLoadNT);
+        // keep the math of the other tile from being scheduled ahead of
+        // these loads (it would delay the prefetch by a whole compute phase)
+        __builtin_amdgcn_sched_barrier(0);
+    }
 
-    auto compute = [&](const Tile<R, CPL, OWN>& t, int64_t b) {
-        const int64_t row0 = b * BATCH;
-        const uint32_t nvalid = (uint32_t)min((int64_t)BATCH, p.N - row0);
+    // Adds the batch's rows (the first nvalid row slots are real) into f and
+    // g.  rbuf: this wave's LDS slice of RPW * R values.
+    __device__ __forceinline__ void compute(const Tile& t, uint32_t nvalid, rtype* rbuf) {
         // partial dot products and the transposed reduction
         double uo[OWN];
         if constexpr (F64) {
@@ -452,13 +501,13 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
             if (ok && unique) facc += tt;
             if (unique) {
                 const int j = R >= LPR ? cl * OWN + o : cl / REP;
-                rbuf[wave][seg][j] = ok ? (rtype)rr : (rtype)0;
+                rbuf[seg * R + j] = ok ? (rtype)rr : (rtype)0;
             }
         }
         __builtin_amdgcn_wave_barrier();
         rtype rs[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) rs[j] = rbuf[wave][seg][j];
+        for (int j = 0; j < R; ++j) rs[j] = rbuf[seg * R + j];
         __builtin_amdgcn_wave_barrier();
         // gradient contribution from the same registers
         if constexpr (F64) {
@@ -479,8 +528,13 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
             for (int j = 0; j < R; ++j)
 #pragma unroll
                 for (int i = 0; i < CPL; ++i) {
+                    u32x4 raw = t.x[j][i];
+                    // Decode again rather than keep the decoded tile of the
+                    // dot-product phase alive (VE floats per 4 raw registers):
+                    // the empty asm hides that raw is unchanged.
+                    if constexpr (VE > 4) asm volatile("" : "+v"(raw));
                     float xv[VE];
-                    decode_chunk<DT>(t.x[j][i], xv);
+                    decode_chunk<DT>(raw, xv);
 #pragma unroll
                     for (int e = 0; e < VE; ++e) g32[i][e] = fmaf(rs[j], xv[e], g32[i][e]);
                 }
@@ -489,39 +543,91 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
 #pragma unroll
                 for (int e = 0; e < VE; ++e) g64[i][e] += (double)g32[i][e];
         }
-    };
-
-    // two tiles in flight: the loads of batch b+1 overlap the math of batch b
-    Tile<R, CPL, OWN> ta, tb;
-    if (bfirst < blast) load(ta, bfirst);
-    for (int64_t b = bfirst; b < blast; b += 2 * bstep) {
-        if (b + bstep < blast) load(tb, b + bstep);
-        compute(ta, b);
-        if (b + bstep >= blast) break;
-        if (b + 2 * bstep < blast) load(ta, b + 2 * bstep);
-        compute(tb, b + bstep);
     }
 
-    // ---- block merge: segments of a wave, then waves in LDS ----
-#pragma unroll
-    for (int i = 0; i < CPL; ++i)
-#pragma unroll
-        for (int e = 0; e < VE; ++e) g64[i][e] = cross_segment_sum<LPR>(g64[i][e]);
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) facc += __shfl_xor(facc, d, 64);
+    // Streams rows [r0, r1) of X / y (absolute row indices; X and y are the
+    // bases of the whole matrix), batch by batch with one batch prefetched.
+    __device__ __forceinline__ void stream_rows(const unsigned char* X, const uint8_t* y,
+                                                int64_t r0, int64_t r1, rtype* rbuf) {
+        Tile ta, tb;
+        load(ta, X, y, r0, r1 - r0);
+        for (int64_t b = r0; b < r1; b += 2 * BATCH) {
+            load(tb, X, y, b + BATCH, r1 - b - BATCH);
+            compute(ta, (uint32_t)min((int64_t)BATCH, r1 - b), rbuf);
+            if (b + BATCH >= r1) break;
+            load(ta, X, y, b + 2 * BATCH, r1 - b - 2 * BATCH);
+            compute(tb, (uint32_t)min((int64_t)BATCH, r1 - b - BATCH), rbuf);
+        }
+    }
 
-    // Waves add their slices into one LDS vector in wave order.
+    // Column sums over the segments of the wave (every lane of segment 0
+    // ends with its columns' totals) and the wave total of f (every lane).
+    __device__ __forceinline__ void wave_totals() {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i)
+#pragma unroll
+            for (int e = 0; e < VE; ++e) g64[i][e] = cross_segment_sum<LPR>(g64[i][e]);
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) facc += __shfl_xor(facc, d, 64);
+    }
+};
+
+// ------------------------------------------------------------ plain kernel
+
+template <int DT, int LPR, int CPL, int R, int WPB>
+__global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
+    using WT = WaveTile<DT, LPR, CPL, R>;
+    constexpr int BATCH = WT::BATCH;
+    constexpr int KT = WT::KT;
+    constexpr int VE = WT::VE;
+
+    WT wt;
+    // wave-uniform: keeps the batch bookkeeping and buffer bases in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    wt.init(threadIdx.x & 63, p.K, p.ldx);
+    wt.set_beta(p.beta, p.scale);
+    wt.zero_acc();
+
+    __shared__ typename WT::rtype rbuf[WPB][WT::RPW * R];
+
+    // This wave's batches: first, first + step, ... below last.  Either
+    // grid-strided (all waves sweep memory together) or one contiguous,
+    // balanced range per wave.
+    const int64_t nbatch = (p.N + BATCH - 1) / BATCH;
+    const int64_t tw = (int64_t)gridDim.x * WPB;
+    const int64_t gw = (int64_t)blockIdx.x * WPB + wave;
+    if (p.interleave) {
+        typename WT::Tile ta, tb;
+        const int64_t step = tw * BATCH;
+        const int64_t rend = nbatch * BATCH;
+        int64_t r = gw * BATCH;
+        wt.load(ta, p.X, p.y, r, p.N - r);
+        for (; r < rend; r += 2 * step) {
+            wt.load(tb, p.X, p.y, r + step, p.N - r - step);
+            wt.compute(ta, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r)), rbuf[wave]);
+            if (r + step >= rend) break;
+            wt.load(ta, p.X, p.y, r + 2 * step, p.N - r - 2 * step);
+            wt.compute(tb, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r - step)), rbuf[wave]);
+        }
+    } else {
+        const int64_t r0 = min(p.N, nbatch * gw / tw * BATCH);
+        const int64_t r1 = min(p.N, nbatch * (gw + 1) / tw * BATCH);
+        wt.stream_rows(p.X, p.y, r0, r1, rbuf[wave]);
+    }
+    wt.wave_totals();
+
+    // ---- block merge: waves add their slices into one LDS vector in order ----
     __shared__ double gsh[KT];
     __shared__ double fsh[WPB];
-    if (lane == 0) fsh[wave] = facc;
+    if (wt.lane == 0) fsh[wave] = wt.facc;
     for (int w = 0; w < WPB; ++w) {
-        if (wave == w && seg == 0) {
+        if (wave == w && wt.seg == 0) {
 #pragma unroll
             for (int i = 0; i < CPL; ++i)
 #pragma unroll
                 for (int e = 0; e < VE; ++e) {
-                    const int k = (cl + i * LPR) * VE + e;
-                    gsh[k] = (w == 0 ? 0.0 : gsh[k]) + g64[i][e];
+                    const int k = wt.col(i, e);
+                    gsh[k] = (w == 0 ? 0.0 : gsh[k]) + wt.g64[i][e];
                 }
         }
         __syncthreads();

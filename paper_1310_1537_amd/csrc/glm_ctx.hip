@@ -1,6 +1,7 @@
 // Context, data-set registry, per-stream scratch and error reporting.
 #include "runtime.hpp"
 
+#include <cstdlib>
 #include <cstring>
 
 namespace glmrt {
@@ -15,6 +16,69 @@ void set_error(const char* fmt, ...) {
 }
 
 void clear_error() { t_err[0] = 0; }
+
+glm_status validate_desc(const glm_dataset_desc& dd) {
+    const glm_dataset_desc* d = &dd;
+    const int es = elem_size(d->dtype);
+    if (!es) GLM_FAIL(GLM_EDTYPE, "data set: unknown dtype %d", d->dtype);
+    if (d->N < 0) GLM_FAIL(GLM_EINVAL, "data set: N = %lld < 0", (long long)d->N);
+    if (d->K < 1 || d->K > GLM_K_MAX)
+        GLM_FAIL(GLM_EINVAL, "data set: K = %d outside [1, %d]", d->K, GLM_K_MAX);
+    if (d->ldx < d->K)
+        GLM_FAIL(GLM_EINVAL, "data set: ldx = %lld < K = %d", (long long)d->ldx, d->K);
+    if (d->N > 0 && (!d->X || !d->y)) GLM_FAIL(GLM_EINVAL, "data set: X or y is NULL");
+    if (d->X && ((uintptr_t)d->X % es))
+        GLM_FAIL(GLM_EINVAL, "data set: X not aligned to its %d-byte element", es);
+    if (d->dtype == GLM_FP8_E4M3 && !d->col_scale)
+        GLM_FAIL(GLM_EINVAL, "data set: FP8 data needs col_scale");
+    if (d->dtype != GLM_FP8_E4M3 && d->col_scale)
+        GLM_FAIL(GLM_EINVAL, "data set: col_scale is only for FP8 data");
+    return GLM_OK;
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("GLM_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    long long a;
+    int b;
+    double us;
+    while (std::fscanf(f, "%511s %lld %d %lf", key, &a, &b, &us) == 4) g_tune[key] = TuneEntry{a, b, us};
+    std::fclose(f);
+}
+}  // namespace
+
+bool tune_cache_get(const std::string& key, TuneEntry* e) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *e = it->second;
+    return true;
+}
+
+void tune_cache_put(const std::string& key, const TuneEntry& e) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = e;
+    const char* path = std::getenv("GLM_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return;
+    for (auto& kv : g_tune)
+        std::fprintf(f, "%s %lld %d %.3f\n", kv.first.c_str(), (long long)kv.second.a, kv.second.b,
+                     kv.second.us);
+    std::fclose(f);
+}
 
 glm_status use_device(glm_ctx* ctx) {
     GLM_HIP_CHECK(hipSetDevice(ctx->device));
@@ -110,20 +174,8 @@ glm_status glm_destroy(glm_ctx* ctx) {
 glm_status glm_dataset_register(glm_ctx* ctx, const glm_dataset_desc* d, glm_dataset_id* out) {
     clear_error();
     if (!ctx || !d || !out) GLM_FAIL(GLM_EINVAL, "glm_dataset_register: NULL argument");
-    const int es = elem_size(d->dtype);
-    if (!es) GLM_FAIL(GLM_EDTYPE, "glm_dataset_register: unknown dtype %d", d->dtype);
-    if (d->N < 0) GLM_FAIL(GLM_EINVAL, "glm_dataset_register: N = %lld < 0", (long long)d->N);
-    if (d->K < 1 || d->K > GLM_K_MAX)
-        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: K = %d outside [1, %d]", d->K, GLM_K_MAX);
-    if (d->ldx < d->K)
-        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: ldx = %lld < K = %d", (long long)d->ldx, d->K);
-    if (d->N > 0 && (!d->X || !d->y)) GLM_FAIL(GLM_EINVAL, "glm_dataset_register: X or y is NULL");
-    if (d->X && ((uintptr_t)d->X % es))
-        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: X not aligned to its %d-byte element", es);
-    if (d->dtype == GLM_FP8_E4M3 && !d->col_scale)
-        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: FP8 data needs col_scale");
-    if (d->dtype != GLM_FP8_E4M3 && d->col_scale)
-        GLM_FAIL(GLM_EINVAL, "glm_dataset_register: col_scale is only for FP8 data");
+    glm_status vs = validate_desc(*d);
+    if (vs != GLM_OK) return vs;
     std::lock_guard<std::mutex> lk(ctx->mu);
     Dataset ds;
     ds.d = *d;

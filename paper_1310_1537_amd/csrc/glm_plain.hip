@@ -19,9 +19,9 @@ struct Inst {
 
 template <int DT, int LPR, int CPL>
 Inst inst() {
-    // about 64 elements of X per lane per batch
+    // 16 row slots of 16 bytes per lane per batch (64 VGPRs per tile)
     constexpr int VE = 16 / glmk::ElemSize<DT>::v;
-    constexpr int RE = DT == glmk::DT_F64 ? 16 : 64 / VE;
+    constexpr int RE = 16;
     constexpr int R = RE / CPL > 0 ? RE / CPL : 1;
     return Inst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, R, WPB>), R};
 }

@@ -111,4 +111,18 @@ glm_status use_device(glm_ctx* ctx);
 // Plan for a data set (defined with the kernel table).
 glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan);
 
+// Argument checks shared by every entry point that takes a data-set descriptor.
+glm_status validate_desc(const glm_dataset_desc& d);
+
+// Tuning cache: the launch choice found for a shape key, kept for the
+// process and, when GLM_TUNE_CACHE names a file, persisted there as text
+// lines "key a b us".
+struct TuneEntry {
+    int64_t a = 0;   // first tuned parameter (e.g. tile rows)
+    int b = 0;       // second tuned parameter (e.g. blocks per compute unit)
+    double us = 0;   // measured time of the choice
+};
+bool tune_cache_get(const std::string& key, TuneEntry* e);
+void tune_cache_put(const std::string& key, const TuneEntry& e);
+
 }  // namespace glmrt

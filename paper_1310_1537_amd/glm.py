@@ -43,6 +43,12 @@ class glm_dataset_desc(ctypes.Structure):
                 ("K", ctypes.c_int32)]
 
 
+class glm_groupset_info_t(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int64), ("blocks", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("split_tiles", ctypes.c_int32), ("tuned_us", ctypes.c_double)]
+
+
 class glm_prior(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_double), ("mean", ctypes.c_void_p),
                 ("mean_per_group", ctypes.c_int32)]
@@ -63,6 +69,10 @@ _SIGS = {
     "glm_dataset_unregister": [_P, _I64],
     "glm_logpost_grad": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P],
     "glm_logpost_grad_host": [_P, _I64, _P, ctypes.POINTER(glm_prior), ctypes.POINTER(_D), _P],
+    "glm_groupset_create": [_P, ctypes.POINTER(glm_dataset_desc), _P, _I32, _I32, _PP],
+    "glm_groupset_destroy": [_P],
+    "glm_groupset_query": [_P, ctypes.c_void_p],
+    "glm_logpost_grad_batched": [_P, _P, _P, ctypes.POINTER(glm_prior), _P, _P],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
     "glm_fp8_col_scales": [_P, _P, _I64, _I32, _I64, _P, _P],
     "glm_quantize_fp8": [_P, _P, _I64, _I32, _I64, _P, _P, _I64, _P],
@@ -177,6 +187,33 @@ def glm_logpost_grad_host(ctx: int, ds: int, beta_host, prior: glm_prior, g_host
     _check(_lib.glm_logpost_grad_host(ctx, ds, b.ctypes.data_as(ctypes.c_void_p),
                                       ctypes.byref(prior), ctypes.byref(f), gp))
     return f.value
+
+
+# ---------------------------------------------------------------- batched
+
+def glm_groupset_create(ctx: int, desc: glm_dataset_desc, offsets, tune: bool = True) -> int:
+    """offsets: host sequence of G + 1 row offsets."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, np.int64)
+    out = ctypes.c_void_p()
+    _check(_lib.glm_groupset_create(ctx, ctypes.byref(desc), off.ctypes.data_as(ctypes.c_void_p),
+                                    len(off) - 1, int(tune), ctypes.byref(out)))
+    return out.value
+
+
+def glm_groupset_destroy(gs: int) -> None:
+    _check(_lib.glm_groupset_destroy(gs))
+
+
+def glm_groupset_query(gs: int) -> dict:
+    info = glm_groupset_info_t()
+    _check(_lib.glm_groupset_query(gs, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def glm_logpost_grad_batched(ctx: int, gs: int, betas, prior: glm_prior, out, stream=None) -> None:
+    _check(_lib.glm_logpost_grad_batched(ctx, gs, _ptr(betas), ctypes.byref(prior), _ptr(out),
+                                         _stream(stream)))
 
 
 # ---------------------------------------------------------------- conversions
