@@ -376,8 +376,79 @@ def bench_batched(args):
     return result
 
 
+def bench_plain_small(args):
+    """Latency-bound small problem: N=10,000, K=20, FP64 X; the 100 seeded
+    points and beta = 0.  Reports device-resident throughput, kernel and
+    host-call latency percentiles, the empty-kernel offload round trip of
+    the paper's Sec. 4.5 on this GPU, and the error against the oracle."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    w = synth.plain_small(n_evals=100)
+    N, K = w.X.shape
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    nb = w.betas.shape[0]
+    betas = torch.from_numpy(np.ascontiguousarray(w.betas)).to(dev)
+    outs = torch.empty((nb, K + 1), dtype=torch.float64, device=dev)
+    ctx = glm.glm_create(0)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
+    prior = glm.make_prior(w.prec)
+    stream = torch.cuda.current_stream()
+    wall, kern_ms = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K, args.warmup,
+                                 args.steps, stream)
+    # all points once more, in order, for the error check
+    for i in range(nb):
+        glm.glm_logpost_grad(ctx, ds, betas[i], prior, outs[i], stream)
+    torch.cuda.synchronize()
+    got = outs.cpu().numpy()
+    g_host = np.empty(K)
+    lat = []
+    for i in range(max(args.latency_calls, 200)):
+        a = time.perf_counter()
+        glm.glm_logpost_grad_host(ctx, ds, w.betas[i % nb], prior, g_host)
+        lat.append(time.perf_counter() - a)
+    lat_us = np.array(lat) * 1e6
+    probe_us = glm.glm_probe_roundtrip(ctx, K, 2000)
+    import oracle
+    t0 = time.perf_counter()
+    ref = [oracle.logpost_grad(w.X, w.y, b, w.prec) for b in w.betas]
+    dt_cpu = time.perf_counter() - t0
+    ef = max(abs(got[i, 0] - ref[i][0]) / abs(ref[i][0]) for i in range(nb))
+    eg = max(np.linalg.norm(got[i, 1:] - ref[i][1]) / max(np.linalg.norm(ref[i][1]), 1e-300)
+             for i in range(nb))
+    bytes_alg = float(N) * K * 8 + N
+    avg = float(kern_ms.mean())
+    glm.glm_dataset_unregister(ctx, ds)
+    glm.glm_destroy(ctx)
+    return {
+        "metric": "logpost+grad evals/s (fused f+g, FP64 result) & HBM GB/s % peak",
+        "value": args.steps / wall, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "plain small: N=10,000 K=20 FP64 X, 100 seeded points + beta=0",
+                   "N": N, "K": K},
+        "roofline": {"bound": "latency", "achieved": bytes_alg / (avg * 1e-3) / 1e9,
+                     "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": bytes_alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, "traffic": None,
+                     "bytes_per_launch": bytes_alg, "launch_us_avg": avg * 1e3},
+        "latency_us": {"kernel_p50": float(np.percentile(kern_ms, 50) * 1e3),
+                       "kernel_p99": float(np.percentile(kern_ms, 99) * 1e3),
+                       "host_call_p50": float(np.percentile(lat_us, 50)),
+                       "host_call_p99": float(np.percentile(lat_us, 99)),
+                       "empty_kernel_roundtrip": probe_us},
+        "err_vs_fp64": {"f_rel_max": ef, "g_rel_norm_max": eg, "points": nb},
+        "cpu_baseline": {"value": nb / dt_cpu, "unit": "evals/s", "cores": 1, "kind": "oracle",
+                         "sample": f"all {nb} points, single-threaded FP64 C"},
+    }
+
+
 WORKLOADS = {"plain_big": bench_plain_big, "precision": bench_precision,
-             "batched": bench_batched}
+             "batched": bench_batched, "plain_small": bench_plain_small}
 
 
 def main() -> int:

@@ -211,6 +211,16 @@ glm_status glm_groupset_query(const glm_groupset* gs, glm_groupset_info* info);
 glm_status glm_logpost_grad_batched(glm_ctx* ctx, glm_groupset* gs, const double* betas,
                                     const glm_prior* prior, double* out, void* stream);
 
+/* -------------------------------------------------------- boundary probe */
+
+/* The offload round trip the paper measures on its GPU (Sec. 4.5): copy K
+ * doubles host -> device, launch an empty kernel, copy one double back and
+ * wait, `iters` times on the context's stream with pinned host buffers.
+ * Writes the mean microseconds per round trip to *us.  This is the latency
+ * floor of any host-driven evaluation (glm_logpost_grad_host).  Errors:
+ * GLM_EINVAL (K < 1, iters < 1, NULL us), GLM_EHIP. */
+glm_status glm_probe_roundtrip(glm_ctx* ctx, int32_t K, int32_t iters, double* us);
+
 /* ----------------------------------------------------- storage conversions */
 
 /* BF16 copy of an FP32 matrix, round to nearest even (NaN stays NaN).

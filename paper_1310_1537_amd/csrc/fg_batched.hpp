@@ -58,7 +58,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
 
     WT wt;
     wt.init(threadIdx.x & 63, K, p.ldx);
-    __shared__ typename WT::rtype rbuf[WPB][WT::RPW * R];
+    __shared__ typename WT::rtype rbuf[WPB][WT::RBUF];
 
     // The wave's items are streamed as one sequence of batches, so the next
     // batch is prefetched across item boundaries too; every item yields at
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
     auto compute = [&](const Tile& t, const Meta& m) {
         if (m.first) {
             citem = p.items[m.it];
-            wt.set_beta(p.betas + (int64_t)citem.group * K, p.scale);
+            wt.set_beta(0, p.betas + (int64_t)citem.group * K, p.scale);
             wt.zero_acc();
         }
         wt.compute(t, (uint32_t)max((int64_t)0, min((int64_t)BATCH, m.r1 - m.row0)), rbuf[wave]);
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
                 for (int e = 0; e < VE; ++e)
                     if (wt.col_ok(i)) {
                         const int k = wt.col(i, e);
-                        double v = wt.g64[i][e];
+                        double v = wt.g64[0][i][e];
                         if constexpr (DT == DT_FP8) v *= (double)p.scale[k];
                         if (dst) {
                             dst[1 + k] = v;
@@ -133,10 +133,10 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
                     }
         }
         if (dst) {
-            if (wt.lane == 0) dst[0] = wt.facc;
+            if (wt.lane == 0) dst[0] = wt.facc[0];
         } else {
             for (int d = 1; d < LPR; d <<= 1) pf += __shfl_xor(pf, d, 64);
-            if (wt.lane == 0) o[0] = wt.facc - 0.5 * p.prec * pf;
+            if (wt.lane == 0) o[0] = wt.facc[0] - 0.5 * p.prec * pf;
         }
     };
 

@@ -54,7 +54,9 @@ template <> struct ElemSize<DT_F32> { static constexpr int v = 4; };
 template <> struct ElemSize<DT_BF16> { static constexpr int v = 2; };
 template <> struct ElemSize<DT_FP8> { static constexpr int v = 1; };
 
-// Kernel parameters (passed by value).
+// Kernel parameters (passed by value).  nb coefficient vectors are
+// evaluated per launch (nb <= the instance's NB; slot b's vectors at stride K,
+// its result at stride 1 + K).
 struct FgParams {
     const unsigned char* X;   // row-major storage, element (n,k) at X + (n*ldx + k)*es
     int64_t ldx;              // leading dimension in elements
@@ -62,12 +64,14 @@ struct FgParams {
     int64_t N;
     int K;
     const float* scale;       // FP8 column scales, else unused
-    const double* beta;       // K doubles
-    const double* mean;       // K doubles or nullptr
-    double prec;
-    double* out;              // 1 + K doubles
-    double* partials;         // nblocks x (1 + K)
-    double* gpart;            // ngroups x (1 + K)
+    const double* beta;       // nb x K doubles
+    const double* mean;       // nb x K doubles or nullptr (zero mean)
+    double prec;              // prior precision when precs is nullptr
+    const double* precs;      // nb precisions or nullptr
+    int nb;                   // coefficient vectors in this launch
+    double* out;              // nb x (1 + K) doubles
+    double* partials;         // nblocks x NB x (1 + K)
+    double* gpart;            // ngroups x NB x (1 + K)
     unsigned* counters;       // ngroups + 1 tickets, zero between launches
     int nblocks;
     int group;                // blocks per merge group
@@ -248,13 +252,14 @@ __device__ __forceinline__ double ordered_sum(const double* a, int n, int64_t st
 }
 
 // Called by every thread of every block after the block has written its
-// partial (1 + K doubles at partials + blockIdx.x * (1 + K)).
+// partial (NB x (1 + K) doubles at partials + blockIdx.x * NB * (1 + K)).
 // NT is the block size (a power of two).
-template <int NT>
+template <int NT, int NB>
 __device__ __forceinline__ void merge_partials(const FgParams& p) {
     __shared__ unsigned s_last;
     __shared__ double s_red[NT];
     const int K1 = p.K + 1;
+    const int W = NB * K1;           // doubles per partial
     const int grp = blockIdx.x / p.group;
     const int b0 = grp * p.group;
     const int b1 = min(p.nblocks, b0 + p.group);
@@ -273,8 +278,8 @@ __device__ __forceinline__ void merge_partials(const FgParams& p) {
     __syncthreads();
     if (!s_last) return;
 
-    for (int k = threadIdx.x; k < K1; k += blockDim.x)
-        p.gpart[(int64_t)grp * K1 + k] = ordered_sum(p.partials + (int64_t)b0 * K1 + k, b1 - b0, K1);
+    for (int k = threadIdx.x; k < W; k += NT)
+        p.gpart[(int64_t)grp * W + k] = ordered_sum(p.partials + (int64_t)b0 * W + k, b1 - b0, W);
     if (threadIdx.x == 0)
         __hip_atomic_store(&p.counters[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
@@ -289,28 +294,35 @@ __device__ __forceinline__ void merge_partials(const FgParams& p) {
     __syncthreads();
     if (!s_last) return;
 
-    // Final sums in group order, plus the Gaussian prior N(mean, prec^-1 I).
-    double pf = 0.0;
-    for (int k = threadIdx.x; k < K1; k += blockDim.x) {
-        const double s = ordered_sum(p.gpart + k, ngroups, K1);
-        if (k == 0) {
-            p.out[0] = s;   // likelihood part; prior added below
-        } else {
-            const double d = p.beta[k - 1] - (p.mean ? p.mean[k - 1] : 0.0);
-            pf += d * d;
-            p.out[k] = s - p.prec * d;
+    // Final sums in group order, plus each slot's Gaussian prior N(m, prec^-1 I).
+    for (int b = 0; b < p.nb; ++b) {
+        const double* beta = p.beta + (int64_t)b * p.K;
+        const double* mean = p.mean ? p.mean + (int64_t)b * p.K : nullptr;
+        const double prec = p.precs ? p.precs[b] : p.prec;
+        double* out = p.out + (int64_t)b * K1;
+        double pf = 0.0;
+        double f_lik = 0.0;
+        for (int k = threadIdx.x; k < K1; k += NT) {
+            const double sacc = ordered_sum(p.gpart + (int64_t)b * K1 + k, ngroups, W);
+            if (k == 0) {
+                f_lik = sacc;   // likelihood part; prior added below
+            } else {
+                const double d = beta[k - 1] - (mean ? mean[k - 1] : 0.0);
+                pf += d * d;
+                out[k] = sacc - prec * d;
+            }
         }
-    }
-    s_red[threadIdx.x] = pf;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+        s_red[threadIdx.x] = pf;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[0] = f_lik - 0.5 * prec * s_red[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        p.out[0] = p.out[0] - 0.5 * p.prec * s_red[0];
+    if (threadIdx.x == 0)
         __hip_atomic_store(&p.counters[ngroups], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
 }
 
 // ------------------------------------------------------------ wave tiles
@@ -320,11 +332,12 @@ constexpr int kRsrcWord3 = 0x00020000;
 // Cache policy of the streaming loads: nontemporal.
 constexpr int kLoadNT = 2;
 
-// The per-wave machinery shared by the plain and the batched kernels: one
-// wave streams batches of BATCH = R * RPW consecutive rows, each lane
-// holding R row slots of CPL 16-byte chunks, and accumulates f and its
-// columns of the gradient.
-template <int DT, int LPR, int CPL, int R>
+// The per-wave machinery shared by the plain, batched and several-beta
+// kernels: one wave streams batches of BATCH = R * RPW consecutive rows, each
+// lane holding R row slots of CPL 16-byte chunks, and accumulates f and its
+// columns of the gradient for NB coefficient vectors at once (the X tile is
+// read from HBM once for all of them).
+template <int DT, int LPR, int CPL, int R, int NB = 1>
 struct WaveTile {
     static constexpr int ES = ElemSize<DT>::v;
     static constexpr int LANES = LPR;             // lanes per row
@@ -336,6 +349,7 @@ struct WaveTile {
     static constexpr bool F64 = DT == DT_F64;
     static constexpr int OWN = R >= LPR ? R / LPR : 1;   // rows owned per lane after reduction
     static constexpr int REP = R >= LPR ? 1 : LPR / R;   // lanes sharing one owned row
+    static constexpr int RBUF = NB * RPW * R;     // LDS values per wave for r
     using rtype = typename std::conditional<F64, double, float>::type;
 
     struct Tile {
@@ -348,10 +362,10 @@ struct WaveTile {
     uint32_t loff[CPL];      // byte offset of this lane's chunk i in row slot 0
     uint32_t yoff[OWN];      // row slot (within a batch) of each owned row
     bool unique;             // this lane accounts its owned rows in f
-    float bh[CPL][VE], bl[CPL][VE];   // beta = bh + bl (FP32 storage kinds)
-    double bd[CPL][VE];               // beta (FP64 storage)
-    double g64[CPL][VE];              // this lane's gradient columns
-    double facc;
+    float bh[NB][CPL][VE], bl[NB][CPL][VE];   // beta = bh + bl (FP32 storage kinds)
+    double bd[NB][CPL][VE];                   // beta (FP64 storage)
+    double g64[NB][CPL][VE];                  // this lane's gradient columns
+    double facc[NB];
 
     __device__ __forceinline__ void init(int lane_, int K, int64_t ldx) {
         lane = lane_;
@@ -376,40 +390,22 @@ struct WaveTile {
     __device__ __forceinline__ int col(int i, int e) const { return (cl + i * LPR) * VE + e; }
     __device__ __forceinline__ bool col_ok(int i) const { return cl + i * LPR < NC; }
 
-    // beta (K doubles); FP8 folds the column scales into it.
-    __device__ __forceinline__ void set_beta(const double* beta, const float* scale) {
+    // Coefficient vector of slot b (K doubles); FP8 folds the column scales in.
+    __device__ __forceinline__ void set_beta(int b, const double* beta, const float* scale) {
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
-                double b = 0.0;
+                double v = 0.0;
                 if (col_ok(i)) {
-                    b = beta[col(i, e)];
-                    if constexpr (DT == DT_FP8) b *= (double)scale[col(i, e)];
+                    v = beta[col(i, e)];
+                    if constexpr (DT == DT_FP8) v *= (double)scale[col(i, e)];
                 }
                 if constexpr (F64) {
-                    bd[i][e] = b;
+                    bd[b][i][e] = v;
                 } else {
-                    bh[i][e] = (float)b;
-                    bl[i][e] = (float)(b - (double)bh[i][e]);
-                }
-            }
-        }
-    }
-
-    // Same from this lane's beta values already in registers.
-    __device__ __forceinline__ void set_beta_values(const double (&b)[CPL][VE], const float* scale) {
-#pragma unroll
-        for (int i = 0; i < CPL; ++i) {
-#pragma unroll
-            for (int e = 0; e < VE; ++e) {
-                double v = b[i][e];
-                if constexpr (DT == DT_FP8) v *= col_ok(i) ? (double)scale[col(i, e)] : 0.0;
-                if constexpr (F64) {
-                    bd[i][e] = v;
-                } else {
-                    bh[i][e] = (float)v;
-                    bl[i][e] = (float)(v - (double)bh[i][e]);
+                    bh[b][i][e] = (float)v;
+                    bl[b][i][e] = (float)(v - (double)bh[b][i][e]);
                 }
             }
         }
@@ -417,10 +413,13 @@ struct WaveTile {
 
     __device__ __forceinline__ void zero_acc() {
 #pragma unroll
-        for (int i = 0; i < CPL; ++i)
+        for (int b = 0; b < NB; ++b) {
 #pragma unroll
-            for (int e = 0; e < VE; ++e) g64[i][e] = 0.0;
-        facc = 0.0;
+            for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                for (int e = 0; e < VE; ++e) g64[b][i][e] = 0.0;
+            facc[b] = 0.0;
+        }
     }
 
     // Loads the batch of rows row0 .. row0 + BATCH - 1 of a row block whose
@@ -453,96 +452,105 @@ struct WaveTile {
     }
 
     // Adds the batch's rows (the first nvalid row slots are real) into f and
-    // g.  rbuf: this wave's LDS slice of RPW * R values.
+    // g of every slot.  rbuf: this wave's LDS slice of RBUF values.
     __device__ __forceinline__ void compute(const Tile& t, uint32_t nvalid, rtype* rbuf) {
-        // partial dot products and the transposed reduction
-        double uo[OWN];
-        if constexpr (F64) {
-            double v[R];
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                double sacc = 0.0;
+        for (int b = 0; b < NB; ++b) {
+            // partial dot products and the transposed reduction
+            double uo[OWN];
+            if constexpr (F64) {
+                double v[R];
 #pragma unroll
-                for (int i = 0; i < CPL; ++i)
+                for (int j = 0; j < R; ++j) {
+                    double sacc = 0.0;
 #pragma unroll
-                    for (int e = 0; e < VE; ++e) sacc = fma(chunk_elem_f64(t.x[j][i], e), bd[i][e], sacc);
-                v[j] = sacc;
-            }
-            seg_reduce<LPR / 2, R, R, double>(v, lane);
+                    for (int i = 0; i < CPL; ++i)
 #pragma unroll
-            for (int o = 0; o < OWN; ++o) uo[o] = v[o];
-        } else {
-            HiLo v[R];
+                        for (int e = 0; e < VE; ++e)
+                            sacc = fma(chunk_elem_f64(t.x[j][i], e), bd[b][i][e], sacc);
+                    v[j] = sacc;
+                }
+                seg_reduce<LPR / 2, R, R, double>(v, lane);
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                float sh = 0.0f, sl = 0.0f;
+                for (int o = 0; o < OWN; ++o) uo[o] = v[o];
+            } else {
+                HiLo v[R];
 #pragma unroll
-                for (int i = 0; i < CPL; ++i) {
-                    float xv[VE];
-                    decode_chunk<DT>(t.x[j][i], xv);
+                for (int j = 0; j < R; ++j) {
+                    float sh = 0.0f, sl = 0.0f;
 #pragma unroll
-                    for (int e = 0; e < VE; ++e) {
-                        sh = fmaf(xv[e], bh[i][e], sh);
-                        sl = fmaf(xv[e], bl[i][e], sl);
+                    for (int i = 0; i < CPL; ++i) {
+                        u32x4 raw = t.x[j][i];
+                        if constexpr (VE > 4 && NB > 1) asm volatile("" : "+v"(raw));
+                        float xv[VE];
+                        decode_chunk<DT>(raw, xv);
+#pragma unroll
+                        for (int e = 0; e < VE; ++e) {
+                            sh = fmaf(xv[e], bh[b][i][e], sh);
+                            sl = fmaf(xv[e], bl[b][i][e], sl);
+                        }
                     }
+                    v[j] = HiLo{sh, sl};
                 }
-                v[j] = HiLo{sh, sl};
+                seg_reduce<LPR / 2, R, R, HiLo>(v, lane);
+#pragma unroll
+                for (int o = 0; o < OWN; ++o) uo[o] = (double)v[o].h + (double)v[o].l;
             }
-            seg_reduce<LPR / 2, R, R, HiLo>(v, lane);
+            // TR map on owned rows (FP64); r to the segment through LDS
 #pragma unroll
-            for (int o = 0; o < OWN; ++o) uo[o] = (double)v[o].h + (double)v[o].l;
-        }
-        // TR map on owned rows (FP64); r to the segment through LDS
-#pragma unroll
-        for (int o = 0; o < OWN; ++o) {
-            double tt, rr;
-            tr_map(uo[o], (double)(t.yb[o] & 1u), tt, rr);
-            const bool ok = yoff[o] < nvalid;
-            if (ok && unique) facc += tt;
-            if (unique) {
-                const int j = R >= LPR ? cl * OWN + o : cl / REP;
-                rbuf[seg * R + j] = ok ? (rtype)rr : (rtype)0;
+            for (int o = 0; o < OWN; ++o) {
+                double tt, rr;
+                tr_map(uo[o], (double)(t.yb[o] & 1u), tt, rr);
+                const bool ok = yoff[o] < nvalid;
+                if (ok && unique) facc[b] += tt;
+                if (unique) {
+                    const int j = R >= LPR ? cl * OWN + o : cl / REP;
+                    rbuf[(b * RPW + seg) * R + j] = ok ? (rtype)rr : (rtype)0;
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
-        rtype rs[R];
 #pragma unroll
-        for (int j = 0; j < R; ++j) rs[j] = rbuf[seg * R + j];
-        __builtin_amdgcn_wave_barrier();
-        // gradient contribution from the same registers
-        if constexpr (F64) {
+        for (int b = 0; b < NB; ++b) {
+            rtype rs[R];
 #pragma unroll
-            for (int j = 0; j < R; ++j)
+            for (int j = 0; j < R; ++j) rs[j] = rbuf[(b * RPW + seg) * R + j];
+            // gradient contribution from the same registers
+            if constexpr (F64) {
+#pragma unroll
+                for (int j = 0; j < R; ++j)
+#pragma unroll
+                    for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                        for (int e = 0; e < VE; ++e)
+                            g64[b][i][e] = fma(rs[j], chunk_elem_f64(t.x[j][i], e), g64[b][i][e]);
+            } else {
+                float g32[CPL][VE];
 #pragma unroll
                 for (int i = 0; i < CPL; ++i)
 #pragma unroll
-                    for (int e = 0; e < VE; ++e)
-                        g64[i][e] = fma(rs[j], chunk_elem_f64(t.x[j][i], e), g64[i][e]);
-        } else {
-            float g32[CPL][VE];
+                    for (int e = 0; e < VE; ++e) g32[i][e] = 0.0f;
 #pragma unroll
-            for (int i = 0; i < CPL; ++i)
+                for (int j = 0; j < R; ++j)
 #pragma unroll
-                for (int e = 0; e < VE; ++e) g32[i][e] = 0.0f;
+                    for (int i = 0; i < CPL; ++i) {
+                        u32x4 raw = t.x[j][i];
+                        // Decode again rather than keep the decoded tile of the
+                        // dot-product phase alive (VE floats per 4 raw registers):
+                        // the empty asm hides that raw is unchanged.
+                        if constexpr (VE > 4) asm volatile("" : "+v"(raw));
+                        float xv[VE];
+                        decode_chunk<DT>(raw, xv);
 #pragma unroll
-            for (int j = 0; j < R; ++j)
+                        for (int e = 0; e < VE; ++e) g32[i][e] = fmaf(rs[j], xv[e], g32[i][e]);
+                    }
 #pragma unroll
-                for (int i = 0; i < CPL; ++i) {
-                    u32x4 raw = t.x[j][i];
-                    // Decode again rather than keep the decoded tile of the
-                    // dot-product phase alive (VE floats per 4 raw registers):
-                    // the empty asm hides that raw is unchanged.
-                    if constexpr (VE > 4) asm volatile("" : "+v"(raw));
-                    float xv[VE];
-                    decode_chunk<DT>(raw, xv);
+                for (int i = 0; i < CPL; ++i)
 #pragma unroll
-                    for (int e = 0; e < VE; ++e) g32[i][e] = fmaf(rs[j], xv[e], g32[i][e]);
-                }
-#pragma unroll
-            for (int i = 0; i < CPL; ++i)
-#pragma unroll
-                for (int e = 0; e < VE; ++e) g64[i][e] += (double)g32[i][e];
+                    for (int e = 0; e < VE; ++e) g64[b][i][e] += (double)g32[i][e];
+            }
         }
+        __builtin_amdgcn_wave_barrier();
     }
 
     // Streams rows [r0, r1) of X / y (absolute row indices; X and y are the
@@ -561,22 +569,26 @@ struct WaveTile {
     }
 
     // Column sums over the segments of the wave (every lane of segment 0
-    // ends with its columns' totals) and the wave total of f (every lane).
+    // ends with its columns' totals) and the wave totals of f (every lane).
     __device__ __forceinline__ void wave_totals() {
 #pragma unroll
-        for (int i = 0; i < CPL; ++i)
+        for (int b = 0; b < NB; ++b) {
 #pragma unroll
-            for (int e = 0; e < VE; ++e) g64[i][e] = cross_segment_sum<LPR>(g64[i][e]);
+            for (int i = 0; i < CPL; ++i)
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) facc += __shfl_xor(facc, d, 64);
+                for (int e = 0; e < VE; ++e) g64[b][i][e] = cross_segment_sum<LPR>(g64[b][i][e]);
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) facc[b] += __shfl_xor(facc[b], d, 64);
+        }
     }
 };
 
 // ------------------------------------------------------------ plain kernel
 
-template <int DT, int LPR, int CPL, int R, int WPB>
+// f and g of p.nb (<= NB) coefficient vectors over all rows of one data set.
+template <int DT, int LPR, int CPL, int R, int WPB, int NB = 1>
 __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
-    using WT = WaveTile<DT, LPR, CPL, R>;
+    using WT = WaveTile<DT, LPR, CPL, R, NB>;
     constexpr int BATCH = WT::BATCH;
     constexpr int KT = WT::KT;
     constexpr int VE = WT::VE;
@@ -585,10 +597,23 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     // wave-uniform: keeps the batch bookkeeping and buffer bases in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     wt.init(threadIdx.x & 63, p.K, p.ldx);
-    wt.set_beta(p.beta, p.scale);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        if (b < p.nb) {
+            wt.set_beta(b, p.beta + (int64_t)b * p.K, p.scale);
+        } else {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                for (int e = 0; e < VE; ++e) {
+                    wt.bh[b][i][e] = wt.bl[b][i][e] = 0.0f;
+                    wt.bd[b][i][e] = 0.0;
+                }
+        }
+    }
     wt.zero_acc();
 
-    __shared__ typename WT::rtype rbuf[WPB][WT::RPW * R];
+    __shared__ typename WT::rtype rbuf[WPB][WT::RBUF];
 
     // This wave's batches: first, first + step, ... below last.  Either
     // grid-strided (all waves sweep memory together) or one contiguous,
@@ -617,34 +642,41 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     wt.wave_totals();
 
     // ---- block merge: waves add their slices into one LDS vector in order ----
-    __shared__ double gsh[KT];
-    __shared__ double fsh[WPB];
-    if (wt.lane == 0) fsh[wave] = wt.facc;
+    const int K1 = p.K + 1;
+    __shared__ double gsh[NB][KT];
+    __shared__ double fsh[WPB][NB];
+    if (wt.lane == 0)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) fsh[wave][b] = wt.facc[b];
     for (int w = 0; w < WPB; ++w) {
         if (wave == w && wt.seg == 0) {
 #pragma unroll
-            for (int i = 0; i < CPL; ++i)
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int e = 0; e < VE; ++e) {
-                    const int k = wt.col(i, e);
-                    gsh[k] = (w == 0 ? 0.0 : gsh[k]) + wt.g64[i][e];
-                }
+                for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) {
+                        const int k = wt.col(i, e);
+                        gsh[b][k] = (w == 0 ? 0.0 : gsh[b][k]) + wt.g64[b][i][e];
+                    }
         }
         __syncthreads();
     }
-    double* part = p.partials + (int64_t)blockIdx.x * (p.K + 1);
-    for (int k = threadIdx.x; k < p.K; k += blockDim.x) {
-        double sacc = gsh[k];
-        if constexpr (DT == DT_FP8) sacc *= (double)p.scale[k];
-        part[1 + k] = sacc;
-    }
-    if (threadIdx.x == 0) {
-        double sacc = 0.0;
+    double* part = p.partials + (int64_t)blockIdx.x * NB * K1;
+    for (int b = 0; b < NB; ++b) {
+        for (int k = threadIdx.x; k < p.K; k += blockDim.x) {
+            double sacc = gsh[b][k];
+            if constexpr (DT == DT_FP8) sacc *= (double)p.scale[k];
+            part[b * K1 + 1 + k] = sacc;
+        }
+        if (threadIdx.x == 0) {
+            double sacc = 0.0;
 #pragma unroll
-        for (int w = 0; w < WPB; ++w) sacc += fsh[w];
-        part[0] = sacc;
+            for (int w = 0; w < WPB; ++w) sacc += fsh[w][b];
+            part[b * K1] = sacc;
+        }
     }
-    merge_partials<WPB * 64>(p);
+    merge_partials<WPB * 64, NB>(p);
 }
 
 }  // namespace glmk

@@ -1,6 +1,7 @@
 // Context, data-set registry, per-stream scratch and error reporting.
 #include "runtime.hpp"
 
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
 
@@ -184,6 +185,42 @@ glm_status glm_dataset_register(glm_ctx* ctx, const glm_dataset_desc* d, glm_dat
     const int64_t id = ctx->next_id++;
     ctx->datasets[id] = ds;
     *out = id;
+    return GLM_OK;
+}
+
+__global__ void k_empty() {}
+
+glm_status glm_probe_roundtrip(glm_ctx* ctx, int32_t K, int32_t iters, double* us) {
+    clear_error();
+    if (!ctx || !us || K < 1 || iters < 1) GLM_FAIL(GLM_EINVAL, "glm_probe_roundtrip: bad argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    double* h = nullptr;
+    double* d = nullptr;
+    GLM_HIP_CHECK(hipHostMalloc((void**)&h, (K + 1) * sizeof(double)));
+    if (hipMalloc((void**)&d, (K + 1) * sizeof(double)) != hipSuccess) {
+        (void)hipHostFree(h);
+        GLM_FAIL(GLM_ENOMEM, "glm_probe_roundtrip: device allocation failed");
+    }
+    for (int k = 0; k <= K; ++k) h[k] = 0.0;
+    hipStream_t s = ctx->own_stream;
+    hipError_t e = hipSuccess;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < iters && e == hipSuccess; ++i) {
+        e = hipMemcpyAsync(d, h, K * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_empty, dim3(1), dim3(1), 0, s);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(h + K, d + K, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    (void)hipFree(d);
+    (void)hipHostFree(h);
+    if (e != hipSuccess) GLM_FAIL(GLM_EHIP, "glm_probe_roundtrip: %s", hipGetErrorString(e));
+    *us = std::chrono::duration<double, std::micro>(t1 - t0).count() / iters;
     return GLM_OK;
 }
 

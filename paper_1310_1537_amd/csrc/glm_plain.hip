@@ -121,6 +121,8 @@ static glm_status launch_plain(glm_ctx* ctx, const Dataset& ds, const double* be
     p.beta = beta;
     p.mean = prior->mean;
     p.prec = prior->prec;
+    p.precs = nullptr;
+    p.nb = 1;
     p.out = out;
     p.partials = s->partials;
     p.gpart = s->gpart;

@@ -73,6 +73,7 @@ _SIGS = {
     "glm_groupset_destroy": [_P],
     "glm_groupset_query": [_P, ctypes.c_void_p],
     "glm_logpost_grad_batched": [_P, _P, _P, ctypes.POINTER(glm_prior), _P, _P],
+    "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
     "glm_fp8_col_scales": [_P, _P, _I64, _I32, _I64, _P, _P],
     "glm_quantize_fp8": [_P, _P, _I64, _I32, _I64, _P, _P, _I64, _P],
@@ -214,6 +215,12 @@ def glm_groupset_query(gs: int) -> dict:
 def glm_logpost_grad_batched(ctx: int, gs: int, betas, prior: glm_prior, out, stream=None) -> None:
     _check(_lib.glm_logpost_grad_batched(ctx, gs, _ptr(betas), ctypes.byref(prior), _ptr(out),
                                          _stream(stream)))
+
+
+def glm_probe_roundtrip(ctx: int, K: int, iters: int = 1000) -> float:
+    us = ctypes.c_double()
+    _check(_lib.glm_probe_roundtrip(ctx, K, iters, ctypes.byref(us)))
+    return us.value
 
 
 # ---------------------------------------------------------------- conversions
