@@ -153,6 +153,19 @@ glm_status glm_dataset_unregister(glm_ctx* ctx, glm_dataset_id id);
 glm_status glm_logpost_grad(glm_ctx* ctx, glm_dataset_id id, const double* beta,
                             const glm_prior* prior, double* out, void* stream);
 
+/* Several coefficient vectors on one data set (e.g. many MCMC chains): f and
+ * g for each of betas[0..nb-1], with X streamed once per pass of up to 8
+ * vectors (the pass width is the largest of 8, 4, 2 that the instance's
+ * register budget allows for this K and dtype; larger nb runs several passes).
+ *   betas  device, nb x K doubles
+ *   prior  host struct; prior->mean NULL (zero) or device nb x K doubles
+ *          (row b is the mean for betas row b); prec shared
+ *   out    device, nb x (1 + K) doubles, row b = [f_b, g_b]
+ * A vector's result does not depend on the other vectors of its pass.
+ * Errors: as glm_logpost_grad. */
+glm_status glm_logpost_grad_multi(glm_ctx* ctx, glm_dataset_id id, const double* betas,
+                                  int32_t nb, const glm_prior* prior, double* out, void* stream);
+
 /* Host-buffer form mirroring the paper's routine: copies beta (and the
  * prior mean, if any) to the device, launches, copies f and g back and waits.
  *   beta_host  K doubles;  prior->mean host K doubles or NULL
@@ -210,6 +223,86 @@ glm_status glm_groupset_query(const glm_groupset* gs, glm_groupset_info* info);
  * GLM_EHIP. */
 glm_status glm_logpost_grad_batched(glm_ctx* ctx, glm_groupset* gs, const double* betas,
                                     const glm_prior* prior, double* out, void* stream);
+
+/* ----------------------------------------------------------------- server */
+
+/* Request server for many concurrent MCMC chains.  Callers submit f + g
+ * requests (one beta each) for registered data sets and collect results by
+ * ticket.  A scheduler thread packs queued requests of one data set into a
+ * single pass over X that evaluates up to max_beta_per_pass coefficient
+ * vectors (glm_logpost_grad_multi's kernels), and keeps up to n_slots passes
+ * in flight on n_streams streams: requests arriving while passes run join the
+ * next free slot (continuous batching).  A request's result does not depend
+ * on which other requests share its pass (bitwise).
+ *
+ * Data sets given with host pointers are copied to device memory on first
+ * use (admission) if they fit hbm_budget_bytes together with the resident
+ * ones; otherwise the least recently used data sets with no pass in flight
+ * are evicted first, and if that is not enough the requests wait.  The
+ * offload cost of one host round trip (Sec. 4.5) is paid per pass. */
+typedef struct glm_server glm_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;   /* device bytes the server may hold for data sets */
+    int32_t max_beta_per_pass;   /* 1..8: coefficient vectors per pass over X       */
+    int32_t n_streams;           /* device streams passes rotate over              */
+    int32_t n_slots;             /* passes in flight at most                       */
+    int32_t queue_capacity;      /* queued requests at most (submit: GLM_EAGAIN)    */
+} glm_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, cancelled, failed;
+    uint64_t passes;             /* passes launched                                 */
+    uint64_t betas_in_passes;    /* requests served by them                         */
+    uint64_t admissions, evictions;
+    uint64_t resident_bytes;
+    int32_t resident_datasets;
+    int32_t queue_depth;
+    uint64_t pass_width_hist[9]; /* [w] = passes that carried w requests (1..8)     */
+    double latency_p50_us;       /* submit -> result ready, finished requests       */
+    double latency_p99_us;
+    double latency_mean_us;
+} glm_server_metrics;
+
+/* Starts the scheduler thread.  Errors: GLM_EINVAL, GLM_EHIP. */
+glm_status glm_server_create(glm_ctx* ctx, const glm_server_config* cfg, glm_server** out);
+
+/* Registers a data set with the server.  on_device == 0: desc holds host
+ * pointers (X, y, col_scale) that the caller keeps valid until the server is
+ * destroyed; the server copies them to HBM when needed.  on_device != 0:
+ * device pointers, always resident (counted in the budget, never evicted).
+ * Errors: as glm_dataset_register; GLM_EBUDGET if the data set alone (or, on
+ * device, with the resident ones) exceeds the budget. */
+glm_status glm_server_add_dataset(glm_server* srv, const glm_dataset_desc* desc, int32_t on_device,
+                                  glm_dataset_id* out);
+
+/* Queues one request; copies beta (K doubles, host) and the prior mean (K
+ * doubles, host, or NULL for zero), so the caller may reuse its buffers.
+ * Thread-safe.  Errors: GLM_ENOTFOUND (data set), GLM_EAGAIN (queue full),
+ * GLM_ECANCELLED (server shutting down), GLM_EINVAL. */
+glm_status glm_server_submit(glm_server* srv, glm_dataset_id ds, const double* beta_host,
+                             double prec, const double* mean_host, uint64_t* ticket);
+
+/* Non-blocking: GLM_PENDING if not finished; GLM_OK copies f and g (K
+ * doubles, host; either may be NULL) and retires the ticket; GLM_ECANCELLED
+ * for a request dropped by shutdown (also retired); GLM_ENOTFOUND for an
+ * unknown or retired ticket. */
+glm_status glm_server_poll(glm_server* srv, uint64_t ticket, double* f, double* g_host);
+
+/* As glm_server_poll but blocks until the request is finished. */
+glm_status glm_server_wait(glm_server* srv, uint64_t ticket, double* f, double* g_host);
+
+glm_status glm_server_stats(glm_server* srv, glm_server_metrics* out);
+
+/* Clears the counters and latency record (not the queue). */
+glm_status glm_server_reset_stats(glm_server* srv);
+
+/* Stops accepting requests, cancels queued ones and waits for passes in
+ * flight; results of finished requests stay available to poll. */
+glm_status glm_server_shutdown(glm_server* srv);
+
+/* Shuts down (if needed) and frees the server and its device copies. */
+glm_status glm_server_destroy(glm_server* srv);
 
 /* -------------------------------------------------------- boundary probe */
 

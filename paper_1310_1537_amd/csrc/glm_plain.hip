@@ -102,27 +102,30 @@ glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
     return GLM_OK;
 }
 
-static glm_status launch_plain(glm_ctx* ctx, const Dataset& ds, const double* beta,
-                               const glm_prior* prior, double* out, void* stream) {
-    const Plan& pl = ds.plan;
-    const int K1 = ds.d.K + 1;
+void scratch_need(const Plan& pl, int K, int NB, size_t* n_partials, size_t* n_gpart,
+                  size_t* n_counters) {
+    const size_t W = (size_t)NB * (K + 1);
     const int ngroups = (pl.nblocks + pl.group - 1) / pl.group;
-    Scratch* s = nullptr;
-    glm_status st = get_scratch(ctx, stream, (size_t)pl.nblocks * K1, (size_t)ngroups * K1,
-                                (size_t)ngroups + 1, &s);
-    if (st != GLM_OK) return st;
+    *n_partials = (size_t)pl.nblocks * W;
+    *n_gpart = (size_t)ngroups * W;
+    *n_counters = (size_t)ngroups + 1;
+}
+
+glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
+                        const double* betas, const double* means, const double* precs,
+                        double prec, int nb, double* out, Scratch* s, hipStream_t stream) {
     glmk::FgParams p;
-    p.X = static_cast<const unsigned char*>(ds.d.X);
-    p.ldx = ds.d.ldx;
-    p.y = ds.d.y;
-    p.N = ds.d.N;
-    p.K = ds.d.K;
-    p.scale = ds.d.col_scale;
-    p.beta = beta;
-    p.mean = prior->mean;
-    p.prec = prior->prec;
-    p.precs = nullptr;
-    p.nb = 1;
+    p.X = static_cast<const unsigned char*>(d.X);
+    p.ldx = d.ldx;
+    p.y = d.y;
+    p.N = d.N;
+    p.K = d.K;
+    p.scale = d.col_scale;
+    p.beta = betas;
+    p.mean = means;
+    p.prec = prec;
+    p.precs = precs;
+    p.nb = nb;
     p.out = out;
     p.partials = s->partials;
     p.gpart = s->gpart;
@@ -130,10 +133,21 @@ static glm_status launch_plain(glm_ctx* ctx, const Dataset& ds, const double* be
     p.nblocks = pl.nblocks;
     p.group = pl.group;
     p.interleave = pl.interleave;
+    (void)NB;
     void* args[] = {&p};
-    GLM_HIP_CHECK(hipLaunchKernel(pl.fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0,
-                                  (hipStream_t)stream));
+    GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0, stream));
     return GLM_OK;
+}
+
+static glm_status launch_plain(glm_ctx* ctx, const Dataset& ds, const double* beta,
+                               const glm_prior* prior, double* out, void* stream) {
+    size_t np, ng, nc;
+    scratch_need(ds.plan, ds.d.K, 1, &np, &ng, &nc);
+    Scratch* s = nullptr;
+    glm_status st = get_scratch(ctx, stream, np, ng, nc, &s);
+    if (st != GLM_OK) return st;
+    return launch_fused(ds.d, ds.plan, ds.plan.fn, 1, beta, prior->mean, nullptr, prior->prec, 1,
+                        out, s, (hipStream_t)stream);
 }
 
 }  // namespace glmrt

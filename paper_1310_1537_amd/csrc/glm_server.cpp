@@ -1,0 +1,570 @@
+// Request server: many MCMC chains submit f + g requests for data sets kept
+// resident in HBM; a scheduler thread batches requests of the same data set
+// into one several-beta pass over X and keeps up to n_slots passes in flight
+// on n_streams streams (continuous batching: requests that arrive while
+// passes run are packed into the next free slot).  Data sets are admitted to
+// device memory on first use within an HBM budget, evicting the least
+// recently used idle ones when needed.
+//
+// The offload cost of a host-driven call is the reason for this design
+// (Sec. 4.5): one transfer + launch pays for up to NB evaluations.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+#include "runtime.hpp"
+
+using Clock = std::chrono::steady_clock;
+
+namespace glmrt {
+namespace {
+
+struct Request {
+    uint64_t ticket;
+    int64_t ds;
+    double prec;
+    bool has_mean;
+    std::vector<double> beta, mean;
+    Clock::time_point t_submit;
+};
+
+enum { R_PENDING = 0, R_DONE = 1, R_CANCELLED = 2, R_FAILED = 3 };
+
+struct Result {
+    int state = R_PENDING;
+    double f = 0.0;
+    std::vector<double> g;
+};
+
+struct SDataset {
+    glm_dataset_desc src;     // as given (host or device pointers)
+    bool on_device = false;   // caller-owned device buffers: always resident, never evicted
+    bool resident = false;
+    glm_dataset_desc dev{};   // device copy in use
+    void* mem = nullptr;      // server allocation (host-sourced data sets)
+    size_t bytes = 0;
+    uint64_t last_use = 0;
+    int inflight = 0;
+    Plan plan;
+    MultiInst mi;             // several-beta instance (or plan.fn with NB = 1)
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    int64_t ds = 0;
+    int nb = 0;
+    std::vector<uint64_t> tickets;
+    std::vector<Clock::time_point> t_submit;
+    // staging: [betas NB*K][means NB*K][precs NB] in, [NB*(K+1)] out
+    double* h_in = nullptr;
+    double* h_out = nullptr;
+    double* d_in = nullptr;
+    double* d_out = nullptr;
+    size_t cap_in = 0, cap_out = 0;   // doubles
+    Scratch scratch;
+};
+
+}  // namespace
+}  // namespace glmrt
+
+using namespace glmrt;
+
+struct glm_server {
+    glm_ctx* ctx = nullptr;
+    glm_server_config cfg{};
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    bool accepting = true;
+    std::deque<Request> queue;
+    std::unordered_map<uint64_t, Result> results;
+    std::map<int64_t, SDataset> datasets;   // references stay valid as sets are added
+    int64_t next_ds = 1;
+    std::atomic<uint64_t> next_ticket{1};
+    std::vector<Slot> slots;
+    std::vector<hipStream_t> streams;
+    uint64_t use_clock = 0;
+    size_t resident_bytes = 0;
+    // statistics
+    uint64_t submitted = 0, completed = 0, cancelled = 0, failed = 0;
+    uint64_t passes = 0, betas_in_passes = 0, admissions = 0, evictions = 0;
+    uint64_t hist[9] = {0};
+    std::vector<float> lat_us;   // submit -> completion of finished requests
+    std::string sched_error;
+};
+
+namespace glmrt {
+namespace {
+
+size_t data_bytes(const glm_dataset_desc& d) {
+    const size_t es = elem_size(d.dtype);
+    size_t b = (size_t)d.N * d.ldx * es + (size_t)d.N;
+    if (d.col_scale) b += (size_t)d.K * 4;
+    return b;
+}
+
+// Frees the server's copy of an idle host-sourced data set.
+void evict(glm_server* s, SDataset& ds) {
+    if (ds.mem) (void)hipFree(ds.mem);
+    ds.mem = nullptr;
+    ds.resident = false;
+    s->resident_bytes -= ds.bytes;
+    s->evictions++;
+}
+
+// 1: resident now, 0: must wait (budget held by busy data sets), -1: error.
+int admit(glm_server* s, SDataset& ds) {
+    if (ds.resident) return 1;
+    while (s->resident_bytes + ds.bytes > s->cfg.hbm_budget_bytes) {
+        SDataset* lru = nullptr;
+        for (auto& kv : s->datasets) {
+            SDataset& o = kv.second;
+            if (o.resident && !o.on_device && o.inflight == 0 && (!lru || o.last_use < lru->last_use))
+                lru = &o;
+        }
+        if (!lru) return 0;
+        evict(s, *lru);
+    }
+    const size_t es = elem_size(ds.src.dtype);
+    const size_t xb = (size_t)ds.src.N * ds.src.ldx * es;
+    const size_t xb_al = (xb + 255) / 256 * 256;
+    const size_t yb_al = ((size_t)ds.src.N + 255) / 256 * 256;
+    const size_t sb = ds.src.col_scale ? (size_t)ds.src.K * 4 : 0;
+    void* mem = nullptr;
+    if (hipMalloc(&mem, xb_al + yb_al + sb + 256) != hipSuccess) {
+        s->sched_error = "device allocation for a data set failed";
+        return -1;
+    }
+    char* base = (char*)mem;
+    ds.dev = ds.src;
+    ds.dev.X = base;
+    ds.dev.y = (const uint8_t*)(base + xb_al);
+    ds.dev.col_scale = sb ? (const float*)(base + xb_al + yb_al) : nullptr;
+    hipError_t e = hipSuccess;
+    if (xb) e = hipMemcpy((void*)ds.dev.X, ds.src.X, xb, hipMemcpyHostToDevice);
+    if (e == hipSuccess && ds.src.N) e = hipMemcpy((void*)ds.dev.y, ds.src.y, ds.src.N, hipMemcpyHostToDevice);
+    if (e == hipSuccess && sb) e = hipMemcpy((void*)ds.dev.col_scale, ds.src.col_scale, sb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        s->sched_error = hipGetErrorString(e);
+        return -1;
+    }
+    ds.mem = mem;
+    ds.resident = true;
+    s->resident_bytes += ds.bytes;
+    s->admissions++;
+    return 1;
+}
+
+bool ensure_slot_capacity(Slot& sl, int NB, int K, const Plan& pl) {
+    const size_t need_in = (size_t)NB * (2 * K + 1), need_out = (size_t)NB * (K + 1);
+    if (sl.cap_in < need_in || sl.cap_out < need_out) {
+        if (sl.h_in) (void)hipHostFree(sl.h_in);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        if (sl.d_in) (void)hipFree(sl.d_in);
+        sl.h_in = sl.h_out = sl.d_in = nullptr;
+        sl.d_out = nullptr;
+        sl.cap_in = sl.cap_out = 0;
+        if (hipHostMalloc((void**)&sl.h_in, need_in * 8) != hipSuccess) return false;
+        if (hipHostMalloc((void**)&sl.h_out, need_out * 8) != hipSuccess) return false;
+        if (hipMalloc((void**)&sl.d_in, (need_in + need_out) * 8) != hipSuccess) return false;
+        sl.d_out = sl.d_in + need_in;
+        sl.cap_in = need_in;
+        sl.cap_out = need_out;
+    }
+    size_t np, ng, nc;
+    scratch_need(pl, K, NB, &np, &ng, &nc);
+    Scratch& sc = sl.scratch;
+    if (!sc.base || sc.cap_partials < np || sc.cap_gpart < ng || sc.cap_counters < nc) {
+        if (sc.base) (void)hipFree(sc.base);
+        sc = Scratch{};
+        const size_t bytes = (np + ng) * 8 + nc * 4;
+        if (hipMalloc(&sc.base, bytes) != hipSuccess) return false;
+        sc.partials = (double*)sc.base;
+        sc.gpart = sc.partials + np;
+        sc.counters = (unsigned*)(sc.gpart + ng);
+        sc.cap_partials = np;
+        sc.cap_gpart = ng;
+        sc.cap_counters = nc;
+        if (hipMemsetAsync(sc.counters, 0, nc * 4, sl.stream) != hipSuccess) return false;
+    }
+    return true;
+}
+
+// Completes finished passes; returns true if any finished.
+bool reap(glm_server* s) {
+    bool any = false;
+    for (Slot& sl : s->slots) {
+        if (!sl.busy || hipEventQuery(sl.done) != hipSuccess) continue;
+        const Clock::time_point now = Clock::now();
+        std::lock_guard<std::mutex> lk(s->mu);
+        SDataset& ds = s->datasets[sl.ds];
+        const int K = ds.src.K;
+        for (int i = 0; i < sl.nb; ++i) {
+            Result& r = s->results[sl.tickets[i]];
+            r.state = R_DONE;
+            r.f = sl.h_out[(size_t)i * (K + 1)];
+            r.g.assign(sl.h_out + (size_t)i * (K + 1) + 1, sl.h_out + (size_t)(i + 1) * (K + 1));
+            s->lat_us.push_back(
+                (float)std::chrono::duration<double, std::micro>(now - sl.t_submit[i]).count());
+        }
+        s->completed += sl.nb;
+        ds.inflight--;
+        sl.busy = false;
+        any = true;
+    }
+    if (any) s->cv.notify_all();
+    return any;
+}
+
+// Starts at most one pass on a free slot; returns true if it did.
+bool dispatch(glm_server* s) {
+    Slot* sl = nullptr;
+    for (Slot& c : s->slots)
+        if (!c.busy) {
+            sl = &c;
+            break;
+        }
+    if (!sl) return false;
+    std::vector<Request> batch;
+    SDataset* dsp = nullptr;
+    int64_t dsid = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->queue.empty()) return false;
+        // oldest request first; data sets that must wait for memory are skipped
+        for (size_t qi = 0; qi < s->queue.size() && !dsp; ++qi) {
+            const int64_t cand = s->queue[qi].ds;
+            SDataset& ds = s->datasets[cand];
+            const int a = admit(s, ds);
+            if (a < 0) {
+                // fail every queued request of this data set
+                for (auto it = s->queue.begin(); it != s->queue.end();) {
+                    if (it->ds == cand) {
+                        s->results[it->ticket].state = R_FAILED;
+                        s->failed++;
+                        it = s->queue.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+                s->cv.notify_all();
+                return true;
+            }
+            if (a == 0) continue;
+            dsp = &ds;
+            dsid = cand;
+        }
+        if (!dsp) return false;
+        const int NB = dsp->mi.fn ? dsp->mi.NB : 1;
+        for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < NB;) {
+            if (it->ds == dsid) {
+                batch.push_back(std::move(*it));
+                it = s->queue.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        dsp->inflight++;
+        dsp->last_use = ++s->use_clock;
+    }
+    SDataset& ds = *dsp;
+    const int K = ds.src.K;
+    const int NB = ds.mi.fn ? ds.mi.NB : 1;
+    const void* fn = ds.mi.fn ? ds.mi.fn : ds.plan.fn;
+    const int nb = (int)batch.size();
+    bool ok = ensure_slot_capacity(*sl, NB, K, ds.plan);
+    bool has_mean = false;
+    for (const Request& r : batch) has_mean |= r.has_mean;
+    if (ok) {
+        double* hb = sl->h_in;
+        double* hm = hb + (size_t)NB * K;
+        double* hp = hm + (size_t)NB * K;
+        for (int i = 0; i < nb; ++i) {
+            std::memcpy(hb + (size_t)i * K, batch[i].beta.data(), K * 8);
+            if (batch[i].has_mean)
+                std::memcpy(hm + (size_t)i * K, batch[i].mean.data(), K * 8);
+            else
+                std::fill(hm + (size_t)i * K, hm + (size_t)(i + 1) * K, 0.0);
+            hp[i] = batch[i].prec;
+        }
+        // copy only what the pass reads: betas, then means (if any) and precs
+        ok = hipMemcpyAsync(sl->d_in, hb, (size_t)nb * K * 8, hipMemcpyHostToDevice, sl->stream) == hipSuccess;
+        if (ok && has_mean)
+            ok = hipMemcpyAsync(sl->d_in + (size_t)NB * K, hm, (size_t)nb * K * 8, hipMemcpyHostToDevice,
+                                sl->stream) == hipSuccess;
+        if (ok)
+            ok = hipMemcpyAsync(sl->d_in + (size_t)2 * NB * K, hp, (size_t)nb * 8, hipMemcpyHostToDevice,
+                                sl->stream) == hipSuccess;
+        if (ok)
+            ok = launch_fused(ds.dev, ds.plan, fn, NB, sl->d_in,
+                              has_mean ? sl->d_in + (size_t)NB * K : nullptr,
+                              sl->d_in + (size_t)2 * NB * K, 0.0, nb, sl->d_out, &sl->scratch,
+                              sl->stream) == GLM_OK;
+        if (ok)
+            ok = hipMemcpyAsync(sl->h_out, sl->d_out, (size_t)nb * (K + 1) * 8, hipMemcpyDeviceToHost,
+                                sl->stream) == hipSuccess;
+        if (ok) ok = hipEventRecord(sl->done, sl->stream) == hipSuccess;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!ok) {
+        for (const Request& r : batch) s->results[r.ticket].state = R_FAILED;
+        s->failed += nb;
+        ds.inflight--;
+        s->sched_error = "pass launch failed";
+        s->cv.notify_all();
+        return true;
+    }
+    sl->busy = true;
+    sl->ds = dsid;
+    sl->nb = nb;
+    sl->tickets.clear();
+    sl->t_submit.clear();
+    for (const Request& r : batch) {
+        sl->tickets.push_back(r.ticket);
+        sl->t_submit.push_back(r.t_submit);
+    }
+    s->passes++;
+    s->betas_in_passes += nb;
+    s->hist[std::min(nb, 8)]++;
+    return true;
+}
+
+void scheduler(glm_server* s) {
+    (void)hipSetDevice(s->ctx->device);
+    while (true) {
+        bool progress = reap(s);
+        while (dispatch(s)) progress = true;
+        bool busy = false;
+        for (Slot& sl : s->slots) busy |= sl.busy;
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->stop && !busy && (s->queue.empty() || !s->accepting)) break;
+        if (!progress) {
+            if (busy)
+                s->cv.wait_for(lk, std::chrono::microseconds(5));
+            else
+                s->cv.wait_for(lk, std::chrono::milliseconds(2),
+                               [&] { return s->stop || !s->queue.empty(); });
+        }
+    }
+}
+
+}  // namespace
+}  // namespace glmrt
+
+extern "C" {
+
+glm_status glm_server_create(glm_ctx* ctx, const glm_server_config* cfg, glm_server** out) {
+    clear_error();
+    if (!ctx || !cfg || !out) GLM_FAIL(GLM_EINVAL, "glm_server_create: NULL argument");
+    *out = nullptr;
+    if (cfg->max_beta_per_pass < 1 || cfg->n_streams < 1 || cfg->n_slots < 1 || cfg->queue_capacity < 1)
+        GLM_FAIL(GLM_EINVAL, "glm_server_create: counts must be >= 1");
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    std::unique_ptr<glm_server> s(new glm_server);
+    s->ctx = ctx;
+    s->cfg = *cfg;
+    s->streams.resize(cfg->n_streams);
+    for (auto& st_ : s->streams) GLM_HIP_CHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+    s->slots.resize(cfg->n_slots);
+    for (int i = 0; i < cfg->n_slots; ++i) {
+        s->slots[i].stream = s->streams[i % cfg->n_streams];
+        GLM_HIP_CHECK(hipEventCreateWithFlags(&s->slots[i].done, hipEventDisableTiming));
+    }
+    glm_server* raw = s.get();
+    s->th = std::thread(scheduler, raw);
+    *out = s.release();
+    return GLM_OK;
+}
+
+glm_status glm_server_add_dataset(glm_server* s, const glm_dataset_desc* d, int32_t on_device,
+                                  glm_dataset_id* out) {
+    clear_error();
+    if (!s || !d || !out) GLM_FAIL(GLM_EINVAL, "glm_server_add_dataset: NULL argument");
+    glm_status st = validate_desc(*d);
+    if (st != GLM_OK) return st;
+    SDataset ds;
+    ds.src = *d;
+    ds.on_device = on_device != 0;
+    ds.bytes = data_bytes(*d);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (ds.bytes > s->cfg.hbm_budget_bytes ||
+        (ds.on_device && s->resident_bytes + ds.bytes > s->cfg.hbm_budget_bytes))
+        GLM_FAIL(GLM_EBUDGET, "glm_server_add_dataset: %zu bytes exceed the HBM budget", ds.bytes);
+    // plan on the device layout (16-byte alignment of the server's copy holds)
+    glm_dataset_desc probe = *d;
+    if (!ds.on_device) probe.X = nullptr;
+    st = make_plan(s->ctx, probe, &ds.plan);
+    if (st != GLM_OK) return st;
+    ds.mi = multi_instance(d->dtype, ds.plan.lpr, ds.plan.cpl, s->cfg.max_beta_per_pass);
+    if (ds.on_device) {
+        ds.dev = *d;
+        ds.resident = true;
+        s->resident_bytes += ds.bytes;
+    }
+    const int64_t id = s->next_ds++;
+    s->datasets[id] = ds;
+    *out = id;
+    return GLM_OK;
+}
+
+glm_status glm_server_submit(glm_server* s, glm_dataset_id ds, const double* beta_host, double prec,
+                             const double* mean_host, uint64_t* ticket) {
+    clear_error();
+    if (!s || !beta_host || !ticket) GLM_FAIL(GLM_EINVAL, "glm_server_submit: NULL argument");
+    if (!(prec >= 0.0)) GLM_FAIL(GLM_EINVAL, "glm_server_submit: prior precision < 0");
+    Request r;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->accepting) GLM_FAIL(GLM_ECANCELLED, "glm_server_submit: server is shutting down");
+        auto it = s->datasets.find(ds);
+        if (it == s->datasets.end())
+            GLM_FAIL(GLM_ENOTFOUND, "glm_server_submit: unknown data set %lld", (long long)ds);
+        if ((int64_t)s->queue.size() >= s->cfg.queue_capacity)
+            GLM_FAIL(GLM_EAGAIN, "glm_server_submit: request queue full");
+        const int K = it->second.src.K;
+        r.beta.assign(beta_host, beta_host + K);
+        r.has_mean = mean_host != nullptr;
+        if (mean_host) r.mean.assign(mean_host, mean_host + K);
+        r.ds = ds;
+        r.prec = prec;
+        r.ticket = s->next_ticket++;
+        r.t_submit = Clock::now();
+        s->results[r.ticket] = Result{};
+        *ticket = r.ticket;
+        s->queue.push_back(std::move(r));
+        s->submitted++;
+    }
+    s->cv.notify_all();
+    return GLM_OK;
+}
+
+static glm_status take_result(glm_server* s, uint64_t ticket, double* f, double* g_host) {
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) GLM_FAIL(GLM_ENOTFOUND, "glm_server: unknown ticket %llu", (unsigned long long)ticket);
+    Result& r = it->second;
+    if (r.state == R_PENDING) return GLM_PENDING;
+    const int state = r.state;
+    if (state == R_DONE) {
+        if (f) *f = r.f;
+        if (g_host) std::memcpy(g_host, r.g.data(), r.g.size() * 8);
+    }
+    s->results.erase(it);
+    if (state == R_CANCELLED) GLM_FAIL(GLM_ECANCELLED, "glm_server: request cancelled by shutdown");
+    if (state == R_FAILED) GLM_FAIL(GLM_EHIP, "glm_server: request failed: %s", s->sched_error.c_str());
+    return GLM_OK;
+}
+
+glm_status glm_server_poll(glm_server* s, uint64_t ticket, double* f, double* g_host) {
+    clear_error();
+    if (!s) GLM_FAIL(GLM_EINVAL, "glm_server_poll: NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    return take_result(s, ticket, f, g_host);
+}
+
+glm_status glm_server_wait(glm_server* s, uint64_t ticket, double* f, double* g_host) {
+    clear_error();
+    if (!s) GLM_FAIL(GLM_EINVAL, "glm_server_wait: NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        auto it = s->results.find(ticket);
+        if (it == s->results.end() || it->second.state != R_PENDING) break;
+        s->cv.wait_for(lk, std::chrono::milliseconds(1));
+    }
+    return take_result(s, ticket, f, g_host);
+}
+
+glm_status glm_server_stats(glm_server* s, glm_server_metrics* out) {
+    clear_error();
+    if (!s || !out) GLM_FAIL(GLM_EINVAL, "glm_server_stats: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->cancelled = s->cancelled;
+    out->failed = s->failed;
+    out->passes = s->passes;
+    out->betas_in_passes = s->betas_in_passes;
+    out->admissions = s->admissions;
+    out->evictions = s->evictions;
+    out->resident_bytes = s->resident_bytes;
+    int nres = 0;
+    for (auto& kv : s->datasets) nres += kv.second.resident;
+    out->resident_datasets = nres;
+    out->queue_depth = (int32_t)s->queue.size();
+    for (int i = 0; i < 9; ++i) out->pass_width_hist[i] = s->hist[i];
+    if (!s->lat_us.empty()) {
+        std::vector<float> v = s->lat_us;
+        auto pct = [&](double q) {
+            const size_t k = std::min(v.size() - 1, (size_t)(q * (v.size() - 1)));
+            std::nth_element(v.begin(), v.begin() + k, v.end());
+            return (double)v[k];
+        };
+        out->latency_p50_us = pct(0.50);
+        out->latency_p99_us = pct(0.99);
+        double sum = 0;
+        for (float x : s->lat_us) sum += x;
+        out->latency_mean_us = sum / s->lat_us.size();
+    }
+    return GLM_OK;
+}
+
+glm_status glm_server_reset_stats(glm_server* s) {
+    clear_error();
+    if (!s) GLM_FAIL(GLM_EINVAL, "glm_server_reset_stats: NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->submitted = s->completed = s->cancelled = s->failed = 0;
+    s->passes = s->betas_in_passes = s->admissions = s->evictions = 0;
+    std::memset(s->hist, 0, sizeof(s->hist));
+    s->lat_us.clear();
+    return GLM_OK;
+}
+
+glm_status glm_server_shutdown(glm_server* s) {
+    clear_error();
+    if (!s) GLM_FAIL(GLM_EINVAL, "glm_server_shutdown: NULL server");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->accepting = false;
+        for (Request& r : s->queue) {
+            s->results[r.ticket].state = R_CANCELLED;
+            s->cancelled++;
+        }
+        s->queue.clear();
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    return GLM_OK;
+}
+
+glm_status glm_server_destroy(glm_server* s) {
+    clear_error();
+    if (!s) return GLM_OK;
+    glm_server_shutdown(s);
+    (void)hipSetDevice(s->ctx->device);
+    for (Slot& sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.h_in) (void)hipHostFree(sl.h_in);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        if (sl.d_in) (void)hipFree(sl.d_in);
+        if (sl.scratch.base) (void)hipFree(sl.scratch.base);
+    }
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    for (auto& kv : s->datasets)
+        if (kv.second.mem) (void)hipFree(kv.second.mem);
+    delete s;
+    return GLM_OK;
+}
+
+}  // extern "C"

@@ -111,6 +111,27 @@ glm_status use_device(glm_ctx* ctx);
 // Plan for a data set (defined with the kernel table).
 glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan);
 
+// Kernel instance evaluating up to nb coefficient vectors per pass over X
+// for a plan's row geometry (nb is rounded down to an instantiated 1, 2, 4
+// or 8 that fits the register budget); fn == nullptr if none.
+struct MultiInst {
+    const void* fn = nullptr;
+    int R = 0;
+    int NB = 0;
+};
+MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max);
+
+// Launches a fused kernel instance (NB slots) for nb coefficient vectors
+// (betas nb x K, means nb x K or nullptr, precs nb or nullptr -> prec) into
+// out (nb x (1 + K)); scratch must hold nblocks x NB x (1 + K) partials.
+glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
+                        const double* betas, const double* means, const double* precs,
+                        double prec, int nb, double* out, Scratch* s, hipStream_t stream);
+
+// Scratch sizes a plan needs for an NB-slot instance.
+void scratch_need(const Plan& pl, int K, int NB, size_t* n_partials, size_t* n_gpart,
+                  size_t* n_counters);
+
 // Argument checks shared by every entry point that takes a data-set descriptor.
 glm_status validate_desc(const glm_dataset_desc& d);
 

@@ -49,6 +49,23 @@ class glm_groupset_info_t(ctypes.Structure):
                 ("split_tiles", ctypes.c_int32), ("tuned_us", ctypes.c_double)]
 
 
+class glm_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_beta_per_pass", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32)]
+
+
+class glm_server_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("cancelled", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("passes", ctypes.c_uint64), ("betas_in_passes", ctypes.c_uint64),
+                ("admissions", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
+                ("resident_bytes", ctypes.c_uint64), ("resident_datasets", ctypes.c_int32),
+                ("queue_depth", ctypes.c_int32), ("pass_width_hist", ctypes.c_uint64 * 9),
+                ("latency_p50_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
+                ("latency_mean_us", ctypes.c_double)]
+
+
 class glm_prior(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_double), ("mean", ctypes.c_void_p),
                 ("mean_per_group", ctypes.c_int32)]
@@ -68,11 +85,21 @@ _SIGS = {
     "glm_dataset_register": [_P, ctypes.POINTER(glm_dataset_desc), ctypes.POINTER(_I64)],
     "glm_dataset_unregister": [_P, _I64],
     "glm_logpost_grad": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P],
+    "glm_logpost_grad_multi": [_P, _I64, _P, _I32, ctypes.POINTER(glm_prior), _P, _P],
     "glm_logpost_grad_host": [_P, _I64, _P, ctypes.POINTER(glm_prior), ctypes.POINTER(_D), _P],
     "glm_groupset_create": [_P, ctypes.POINTER(glm_dataset_desc), _P, _I32, _I32, _PP],
     "glm_groupset_destroy": [_P],
     "glm_groupset_query": [_P, ctypes.c_void_p],
     "glm_logpost_grad_batched": [_P, _P, _P, ctypes.POINTER(glm_prior), _P, _P],
+    "glm_server_create": [_P, ctypes.POINTER(glm_server_config), _PP],
+    "glm_server_add_dataset": [_P, ctypes.POINTER(glm_dataset_desc), _I32, ctypes.POINTER(_I64)],
+    "glm_server_submit": [_P, _I64, _P, _D, _P, ctypes.POINTER(ctypes.c_uint64)],
+    "glm_server_poll": [_P, ctypes.c_uint64, ctypes.POINTER(_D), _P],
+    "glm_server_wait": [_P, ctypes.c_uint64, ctypes.POINTER(_D), _P],
+    "glm_server_stats": [_P, ctypes.c_void_p],
+    "glm_server_reset_stats": [_P],
+    "glm_server_shutdown": [_P],
+    "glm_server_destroy": [_P],
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
     "glm_fp8_col_scales": [_P, _P, _I64, _I32, _I64, _P, _P],
@@ -179,6 +206,12 @@ def glm_logpost_grad(ctx: int, ds: int, beta, prior: glm_prior, out, stream=None
                                  _stream(stream)))
 
 
+def glm_logpost_grad_multi(ctx: int, ds: int, betas, nb: int, prior: glm_prior, out,
+                           stream=None) -> None:
+    _check(_lib.glm_logpost_grad_multi(ctx, ds, _ptr(betas), nb, ctypes.byref(prior), _ptr(out),
+                                       _stream(stream)))
+
+
 def glm_logpost_grad_host(ctx: int, ds: int, beta_host, prior: glm_prior, g_host=None):
     """beta_host / prior.mean / g_host: numpy float64 arrays (host).  Returns f."""
     import numpy as np
@@ -215,6 +248,82 @@ def glm_groupset_query(gs: int) -> dict:
 def glm_logpost_grad_batched(ctx: int, gs: int, betas, prior: glm_prior, out, stream=None) -> None:
     _check(_lib.glm_logpost_grad_batched(ctx, gs, _ptr(betas), ctypes.byref(prior), _ptr(out),
                                          _stream(stream)))
+
+
+# ---------------------------------------------------------------- server
+
+def glm_server_create(ctx: int, hbm_budget_bytes: int, max_beta_per_pass: int = 8,
+                      n_streams: int = 4, n_slots: int = 8, queue_capacity: int = 1 << 20) -> int:
+    cfg = glm_server_config(hbm_budget_bytes, max_beta_per_pass, n_streams, n_slots,
+                            queue_capacity)
+    out = ctypes.c_void_p()
+    _check(_lib.glm_server_create(ctx, ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def make_host_desc(X, y, dtype=None, col_scale=None) -> glm_dataset_desc:
+    """Descriptor with host pointers for numpy X (row-major) and y."""
+    import numpy as np
+    assert X.ndim == 2 and X.strides[1] == X.itemsize
+    if dtype is None:
+        dtype = {np.dtype(np.float64): GLM_F64, np.dtype(np.float32): GLM_F32,
+                 np.dtype(np.uint16): GLM_BF16, np.dtype(np.uint8): GLM_FP8_E4M3}[X.dtype]
+    return glm_dataset_desc(X.ctypes.data, X.strides[0] // X.itemsize, dtype,
+                            None if col_scale is None else col_scale.ctypes.data,
+                            y.ctypes.data, X.shape[0], X.shape[1])
+
+
+def glm_server_add_dataset(srv: int, desc: glm_dataset_desc, on_device: bool = False) -> int:
+    out = ctypes.c_int64()
+    _check(_lib.glm_server_add_dataset(srv, ctypes.byref(desc), int(on_device), ctypes.byref(out)))
+    return out.value
+
+
+def glm_server_submit(srv: int, ds: int, beta_host, prec: float, mean_host=None) -> int:
+    """Returns the ticket (raises GlmError with GLM_EAGAIN when the queue is full)."""
+    import numpy as np
+    b = np.ascontiguousarray(beta_host, np.float64)
+    m = None if mean_host is None else np.ascontiguousarray(mean_host, np.float64)
+    t = ctypes.c_uint64()
+    _check(_lib.glm_server_submit(srv, ds, b.ctypes.data_as(ctypes.c_void_p), float(prec),
+                                  None if m is None else m.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(t)))
+    return t.value
+
+
+def glm_server_poll(srv: int, ticket: int, g_host=None):
+    """Returns (status, f); status GLM_OK or GLM_PENDING (others raise)."""
+    f = ctypes.c_double()
+    gp = None if g_host is None else g_host.ctypes.data_as(ctypes.c_void_p)
+    st = _check(_lib.glm_server_poll(srv, ticket, ctypes.byref(f), gp), allow_pending=True)
+    return st, f.value
+
+
+def glm_server_wait(srv: int, ticket: int, g_host=None) -> float:
+    f = ctypes.c_double()
+    gp = None if g_host is None else g_host.ctypes.data_as(ctypes.c_void_p)
+    _check(_lib.glm_server_wait(srv, ticket, ctypes.byref(f), gp))
+    return f.value
+
+
+def glm_server_stats(srv: int) -> dict:
+    st = glm_server_stats_t()
+    _check(_lib.glm_server_stats(srv, ctypes.byref(st)))
+    d = {f: getattr(st, f) for f, _ in st._fields_}
+    d["pass_width_hist"] = list(st.pass_width_hist)
+    return d
+
+
+def glm_server_reset_stats(srv: int) -> None:
+    _check(_lib.glm_server_reset_stats(srv))
+
+
+def glm_server_shutdown(srv: int) -> None:
+    _check(_lib.glm_server_shutdown(srv))
+
+
+def glm_server_destroy(srv: int) -> None:
+    _check(_lib.glm_server_destroy(srv))
 
 
 def glm_probe_roundtrip(ctx: int, K: int, iters: int = 1000) -> float:

@@ -1,0 +1,237 @@
+"""GPU tests of the several-beta pass (glm_logpost_grad_multi) and of the
+request server (continuous batching over resident data sets)."""
+import math
+import threading
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+
+if torch.cuda.is_available():
+    from gpu_helpers import DEV, Ctx, bounds, to_dev  # noqa: E402
+    from paper_1310_1537_amd import glm  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Ctx()
+    yield c.h
+    c.close()
+
+
+def _data(N, K, seed, dtype=np.float32):
+    g = np.random.default_rng(seed)
+    X = g.standard_normal((N, K)).astype(dtype)
+    bt = g.standard_normal(K) / math.sqrt(K)
+    y = (g.random(N) < 1.0 / (1.0 + np.exp(-(X.astype(np.float64) @ bt)))).astype(np.uint8)
+    return X, y, bt
+
+
+def _betas(bt, n, seed):
+    return bt + 0.1 * np.random.default_rng(seed).standard_normal((n, len(bt)))
+
+
+def _check(f, g, Xd, y, beta, prec, mean=None, storage="f32", Xo=None, okw=None):
+    fo, go = oracle.logpost_grad(Xd if Xo is None else Xo, y, beta, prec, mean, **(okw or {}))
+    bf, bg = bounds(Xd, y, beta, fo, go, storage)
+    assert abs(f - fo) <= bf, (f, fo, bf)
+    assert np.all(np.abs(g - go) <= bg)
+
+
+@pytest.mark.parametrize("K", [8, 32, 128, 512])
+@pytest.mark.parametrize("nb", [1, 3, 8, 11])
+def test_multi_against_oracle(ctx, K, nb):
+    X, y, bt = _data(20_011, K, K + nb)
+    B = _betas(bt, nb, 7)
+    Xd, yd = to_dev(X), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
+    out = torch.full((nb, K + 1), float("nan"), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), nb, glm.make_prior(0.01), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for b in range(nb):
+        _check(o[b, 0], o[b, 1:], X.astype(np.float64), y, B[b], 0.01)
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+def test_multi_per_vector_means_and_bf16(ctx):
+    X, y, bt = _data(9_000, 64, 3)
+    Q = oracle.quantize_bf16(X)
+    B = _betas(bt, 5, 8)
+    M = np.random.default_rng(9).standard_normal((5, 64))
+    Qd, yd = to_dev(Q), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
+    out = torch.empty((5, 65), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), 5, glm.make_prior(2.0, to_dev(M)), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for b in range(5):
+        _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 2.0, M[b], Xo=Q,
+               okw={"dtype": "bf16"})
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+def test_multi_result_independent_of_companions(ctx):
+    """Slot 0 of a pass gives the same bits whatever the other slots hold."""
+    X, y, bt = _data(30_000, 128, 4)
+    B = _betas(bt, 8, 10)
+    Xd, yd = to_dev(X), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
+    out8 = torch.empty((8, 129), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), 8, glm.make_prior(0.01), out8)
+    B2 = B.copy()
+    B2[1:] = _betas(bt, 7, 11)
+    out8b = torch.empty((8, 129), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B2), 8, glm.make_prior(0.01), out8b)
+    torch.cuda.synchronize()
+    assert np.array_equal(out8.cpu().numpy()[0], out8b.cpu().numpy()[0])
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+# ------------------------------------------------------------------ server
+
+def _server(ctx, budget=1 << 34, nbmax=8, slots=8, streams=4, qcap=1 << 20):
+    return glm.glm_server_create(ctx, budget, nbmax, streams, slots, qcap)
+
+
+def test_server_results_match_oracle(ctx):
+    sets = [_data(5_000, 8, 20), _data(12_345, 32, 21), _data(3_000, 128, 22, np.float64)]
+    srv = _server(ctx)
+    ids = [glm.glm_server_add_dataset(srv, glm.make_host_desc(X, y)) for X, y, _ in sets]
+    reqs = []
+    rng = np.random.default_rng(23)
+    for i in range(120):
+        d = int(rng.integers(0, 3))
+        beta = sets[d][2] + 0.1 * rng.standard_normal(sets[d][0].shape[1])
+        reqs.append((d, beta, glm.glm_server_submit(srv, ids[d], beta, 0.01)))
+    for d, beta, t in reqs:
+        X, y, _ = sets[d]
+        g = np.empty(X.shape[1])
+        f = glm.glm_server_wait(srv, t, g)
+        _check(f, g, X.astype(np.float64), y, beta, 0.01,
+               storage="f64" if X.dtype == np.float64 else "f32")
+    st = glm.glm_server_stats(srv)
+    assert st["completed"] == 120 and st["failed"] == 0
+    assert st["betas_in_passes"] == 120 and st["passes"] <= 120
+    glm.glm_server_destroy(srv)
+
+
+def test_server_alone_equals_in_mix_bitwise(ctx):
+    """A request's result is the same bits alone in its pass and packed with
+    seven other chains' requests (the slot position may differ too)."""
+    X, y, bt = _data(1_000_000, 128, 30)
+    srv = _server(ctx, slots=1, streams=1)   # one slot: later requests queue up
+    ds = glm.glm_server_add_dataset(srv, glm.make_host_desc(X, y))
+    B = _betas(bt, 16, 31)
+    alone = []
+    for b in range(8):
+        t = glm.glm_server_submit(srv, ds, B[b], 0.01)
+        g = np.empty(128)
+        f = glm.glm_server_wait(srv, t, g)
+        alone.append((f, g))
+    # keep the single slot busy with a pass, queue 8+ requests behind it
+    ts = [glm.glm_server_submit(srv, ds, B[8 + b], 0.01) for b in range(8)]
+    ts = [glm.glm_server_submit(srv, ds, B[(7 - b)], 0.01) for b in range(8)] + ts
+    mixed = {}
+    for k, t in enumerate(ts[:8]):
+        g = np.empty(128)
+        f = glm.glm_server_wait(srv, t, g)
+        mixed[7 - k] = (f, g)
+    for t in ts[8:]:
+        glm.glm_server_wait(srv, t)
+    st = glm.glm_server_stats(srv)
+    assert sum(st["pass_width_hist"][2:]) >= 1, st["pass_width_hist"]   # some packing happened
+    for b in range(8):
+        assert mixed[b][0] == alone[b][0]
+        assert np.array_equal(mixed[b][1], alone[b][1])
+    glm.glm_server_destroy(srv)
+
+
+def test_server_admission_and_eviction(ctx):
+    """Budget for one data set at a time: alternating requests force
+    evictions; results stay exact."""
+    a = _data(40_000, 32, 40)
+    b = _data(40_000, 32, 41)
+    one = 40_000 * 32 * 4 + 40_000
+    srv = _server(ctx, budget=int(1.5 * one), slots=1, streams=1)
+    ia = glm.glm_server_add_dataset(srv, glm.make_host_desc(a[0], a[1]))
+    ib = glm.glm_server_add_dataset(srv, glm.make_host_desc(b[0], b[1]))
+    for r in range(4):
+        for (X, y, bt), i in ((a, ia), (b, ib)):
+            beta = bt + 0.01 * r
+            g = np.empty(32)
+            f = glm.glm_server_wait(srv, glm.glm_server_submit(srv, i, beta, 0.01), g)
+            _check(f, g, X.astype(np.float64), y, beta, 0.01)
+    st = glm.glm_server_stats(srv)
+    assert st["evictions"] >= 6 and st["admissions"] >= 7
+    assert st["resident_datasets"] == 1
+    glm.glm_server_destroy(srv)
+
+
+def test_server_budget_and_unknown_ids(ctx):
+    X, y, _ = _data(1000, 8, 50)
+    srv = _server(ctx, budget=1000)
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_server_add_dataset(srv, glm.make_host_desc(X, y))
+    assert e.value.status == glm.GLM_EBUDGET
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_server_submit(srv, 99, np.zeros(8), 0.01)
+    assert e.value.status == glm.GLM_ENOTFOUND
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_server_poll(srv, 12345)
+    assert e.value.status == glm.GLM_ENOTFOUND
+    glm.glm_server_destroy(srv)
+
+
+def test_server_shutdown_cancels_queued(ctx):
+    X, y, bt = _data(400_000, 64, 60)
+    srv = _server(ctx, slots=1, streams=1)
+    ds = glm.glm_server_add_dataset(srv, glm.make_host_desc(X, y))
+    ts = [glm.glm_server_submit(srv, ds, bt, 0.01) for _ in range(64)]
+    glm.glm_server_shutdown(srv)
+    done = cancelled = 0
+    for t in ts:
+        try:
+            st, _ = glm.glm_server_poll(srv, t)
+            assert st == glm.GLM_OK
+            done += 1
+        except glm.GlmError as e:
+            assert e.status == glm.GLM_ECANCELLED
+            cancelled += 1
+    assert done + cancelled == 64 and cancelled > 0
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_server_submit(srv, ds, bt, 0.01)
+    assert e.value.status == glm.GLM_ECANCELLED
+    glm.glm_server_destroy(srv)
+
+
+def test_server_device_resident_and_threads(ctx):
+    """Device-resident data set, requests from several host threads."""
+    X, y, bt = _data(50_000, 32, 70)
+    Xd, yd = to_dev(X), to_dev(y)
+    srv = _server(ctx)
+    ds = glm.glm_server_add_dataset(srv, glm.make_desc(Xd, yd), on_device=True)
+    res = {}
+
+    def worker(w):
+        rng = np.random.default_rng(100 + w)
+        for i in range(25):
+            beta = bt + 0.1 * rng.standard_normal(32)
+            g = np.empty(32)
+            f = glm.glm_server_wait(srv, glm.glm_server_submit(srv, ds, beta, 0.01), g)
+            res[(w, i)] = (beta, f, g)
+
+    th = [threading.Thread(target=worker, args=(w,)) for w in range(6)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert len(res) == 150
+    for beta, f, g in list(res.values())[::10]:
+        _check(f, g, X.astype(np.float64), y, beta, 0.01)
+    glm.glm_server_destroy(srv)
