@@ -18,7 +18,6 @@ the FP64 CPU oracle's own throughput on this host.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -29,16 +28,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fg_fused_plain_big_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1310_1537_amd", "csrc", f)
-                  for f in ("fg_kernel.hpp", "glm_plain.hip")]
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1310_1537_amd.profiling import kernel_source_hash as h
+    return h()
 
 
 def measured_traffic(bytes_alg: float):
@@ -447,8 +441,139 @@ def bench_plain_small(args):
     }
 
 
-WORKLOADS = {"plain_big": bench_plain_big, "precision": bench_precision,
-             "batched": bench_batched, "plain_small": bench_plain_small}
+def bench_serving(args):
+    """Request server: 64 device-resident data sets (N log-uniform on [1e3,
+    2e6], K from {8, 32, 128, 512}, BF16 or FP32 50/50), 512 chains (8 per
+    data set) sending open-loop Poisson arrivals, each request a fresh beta
+    (the chain's state plus N(0, 0.01^2 I)).  Throughput and submit-to-result
+    latency per arrival rate, with passes of up to 8 vectors and with one
+    request per pass."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    spec = synth.serving_specs()
+    nd = len(spec.N)
+    ctx = glm.glm_create(0)
+    keep = []          # device tensors of the data sets
+    datasets = []      # (K, beta_true, bytes)
+    t0 = time.perf_counter()
+    for i in range(nd):
+        X32, y, bt = synth.serving_dataset(i, spec)
+        Xd = torch.from_numpy(X32).to(dev)
+        yd = torch.from_numpy(y).to(dev)
+        if spec.dtype[i] == "bf16":
+            Q = torch.empty(Xd.shape, dtype=torch.uint16, device=dev)
+            glm.glm_quantize_bf16(ctx, Xd, Q)
+            torch.cuda.synchronize()
+            del Xd
+            keep.append((Q, yd, glm.GLM_BF16))
+            es = 2
+        else:
+            keep.append((Xd, yd, glm.GLM_F32))
+            es = 4
+        datasets.append((int(spec.K[i]), bt, int(spec.N[i]) * (int(spec.K[i]) * es + 1)))
+    total_bytes = sum(d[2] for d in datasets)
+    print(f"[bench] {nd} data sets, {total_bytes / 1e9:.2f} GB, built in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    n_chains = 512
+    pool = 16
+    rng = np.random.default_rng(4)
+    betas = []        # per chain: pool x K
+    for c in range(n_chains):
+        K, bt, _ = datasets[c // 8]
+        state = bt + 0.1 * rng.standard_normal(K)
+        betas.append(np.ascontiguousarray(state + 0.01 * rng.standard_normal((pool, K))))
+    ptr_table = np.array([[b[j].ctypes.data for j in range(pool)] for b in betas], np.uint64)
+
+    def run(nbmax, rate, n_req, seed):
+        srv = glm.glm_server_create(ctx, 200 * (1 << 30), nbmax, 4, 8, 1 << 22)
+        ids = [glm.glm_server_add_dataset(srv, glm.make_desc(X, y, dtype=dt), on_device=True)
+               for X, y, dt in keep]
+        # warm: one pass per data set
+        t = glm.glm_server_submit_many(srv, np.array(ids, np.int64),
+                                       ptr_table[np.arange(nd) * 8, 0], np.full(nd, 0.01))
+        glm.glm_server_wait_many(srv, t)
+        glm.glm_server_reset_stats(srv)
+        arr, chain = synth.poisson_arrivals(rate, n_req, n_chains, seed)
+        ds_of = np.array(ids, np.int64)[chain // 8]
+        ptrs = ptr_table[chain, np.arange(n_req) % pool]
+        precs = np.full(n_req, 0.01)
+        tickets = []
+        i = 0
+        t0 = time.perf_counter()
+        while i < n_req:
+            now = time.perf_counter() - t0
+            j = int(np.searchsorted(arr, now, side="right"))
+            if j > i:
+                tickets.append(glm.glm_server_submit_many(srv, ds_of[i:j], ptrs[i:j], precs[i:j]))
+                i = j
+        for t in tickets:
+            glm.glm_server_wait_many(srv, t)
+        wall = time.perf_counter() - t0
+        st = glm.glm_server_stats(srv)
+        glm.glm_server_destroy(srv)
+        return {"rate_offered": rate, "requests": n_req, "throughput": n_req / wall,
+                "latency_p50_us": st["latency_p50_us"], "latency_p99_us": st["latency_p99_us"],
+                "latency_mean_us": st["latency_mean_us"], "passes": st["passes"],
+                "mean_pass_width": st["betas_in_passes"] / max(1, st["passes"]),
+                "pass_width_hist": st["pass_width_hist"][1:], "failed": st["failed"]}
+
+    rates = [int(r) for r in args.serving_rates.split(",")]
+    res_b, res_1 = [], []
+    for k, r in enumerate(rates):
+        n_req = int(min(r * args.serving_seconds, 400_000))
+        res_b.append(run(8, r, n_req, k))
+        print(f"[bench] batched  rate {r}: {res_b[-1]['throughput']:.0f} req/s "
+              f"p50 {res_b[-1]['latency_p50_us']:.0f} us p99 {res_b[-1]['latency_p99_us']:.0f} us "
+              f"width {res_b[-1]['mean_pass_width']:.2f}", file=sys.stderr, flush=True)
+    for k, r in enumerate(rates[:2] if args.serving_baseline else []):
+        n_req = int(min(r * args.serving_seconds, 100_000))
+        res_1.append(run(1, r, n_req, 10 + k))
+        print(f"[bench] one/pass rate {r}: {res_1[-1]['throughput']:.0f} req/s "
+              f"p50 {res_1[-1]['latency_p50_us']:.0f} us p99 {res_1[-1]['latency_p99_us']:.0f} us",
+              file=sys.stderr, flush=True)
+    glm.glm_destroy(ctx)
+    top = res_b[-1]
+    return {
+        "metric": "logpost+grad requests/s served (fused f+g, FP64 result), p50/p99 latency",
+        "value": top["throughput"], "unit": "requests/s", "n_gpus": 1,
+        "steps": top["requests"], "warmup": nd, "ms_per_step": 1e3 / top["throughput"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32/bf16",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {nd} device-resident data sets ({total_bytes / 1e9:.2f} GB, "
+                               "N log-uniform 1e3..2e6, K in {8,32,128,512}, BF16/FP32 50/50), "
+                               "512 chains, open-loop Poisson arrivals",
+                   "hbm_budget_GB": 200, "max_beta_per_pass": 8, "slots": 8, "streams": 4},
+        "latency_us": {"p50": top["latency_p50_us"], "p99": top["latency_p99_us"]},
+        "by_rate": res_b, "one_request_per_pass": res_1,
+    }
+
+
+def bench_copy(args):
+    """A plain device-to-device copy of a known size (counter calibration)."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return {"metric": "copy", "value": 2 * n / dt / 1e9, "unit": "GB/s (read + write)",
+            "bytes_read": n, "bytes_written": n}
+
+
+WORKLOADS = {"copy": bench_copy, "plain_big": bench_plain_big, "precision": bench_precision,
+             "batched": bench_batched, "plain_small": bench_plain_small,
+             "serving": bench_serving}
 
 
 def main() -> int:
@@ -460,6 +585,10 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0, help="override N (precision workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200)
+    ap.add_argument("--serving-seconds", type=float, default=1.0)
+    ap.add_argument("--serving-rates", default="20000,50000,100000,200000")
+    ap.add_argument("--serving-baseline", type=int, default=1,
+                    help="also run one request per pass at the first two rates")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -283,6 +283,20 @@ glm_status glm_server_add_dataset(glm_server* srv, const glm_dataset_desc* desc,
 glm_status glm_server_submit(glm_server* srv, glm_dataset_id ds, const double* beta_host,
                              double prec, const double* mean_host, uint64_t* ticket);
 
+/* Queues n requests at once (all or none): request i is for data set ds[i]
+ * with coefficient vector betas[i] (host, K doubles of that data set),
+ * precision precs[i] and zero prior mean.  tickets: n entries out.
+ * Errors: GLM_EAGAIN if the queue cannot take all n, else as
+ * glm_server_submit. */
+glm_status glm_server_submit_many(glm_server* srv, int32_t n, const glm_dataset_id* ds,
+                                  const double* const* betas, const double* precs,
+                                  uint64_t* tickets);
+
+/* Waits for n tickets and retires them; f_out (n doubles, may be NULL)
+ * receives f of each finished request (NaN for a cancelled or failed one).
+ * Returns GLM_OK if all finished normally, else the first error met. */
+glm_status glm_server_wait_many(glm_server* srv, int32_t n, const uint64_t* tickets, double* f_out);
+
 /* Non-blocking: GLM_PENDING if not finished; GLM_OK copies f and g (K
  * doubles, host; either may be NULL) and retires the ticket; GLM_ECANCELLED
  * for a request dropped by shutdown (also retired); GLM_ENOTFOUND for an

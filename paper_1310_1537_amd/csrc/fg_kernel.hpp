@@ -452,10 +452,14 @@ struct WaveTile {
     }
 
     // Adds the batch's rows (the first nvalid row slots are real) into f and
-    // g of every slot.  rbuf: this wave's LDS slice of RBUF values.
-    __device__ __forceinline__ void compute(const Tile& t, uint32_t nvalid, rtype* rbuf) {
+    // g of the first nact slots (nact is wave-uniform; the other slots are
+    // skipped, so a partly filled pass costs what it carries).  rbuf: this
+    // wave's LDS slice of RBUF values.
+    __device__ __forceinline__ void compute(const Tile& t, uint32_t nvalid, rtype* rbuf,
+                                            int nact = NB) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+            if (b >= nact) break;
             // partial dot products and the transposed reduction
             double uo[OWN];
             if constexpr (F64) {
@@ -512,6 +516,7 @@ struct WaveTile {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
+            if (b >= nact) break;
             rtype rs[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) rs[j] = rbuf[(b * RPW + seg) * R + j];
@@ -556,15 +561,16 @@ struct WaveTile {
     // Streams rows [r0, r1) of X / y (absolute row indices; X and y are the
     // bases of the whole matrix), batch by batch with one batch prefetched.
     __device__ __forceinline__ void stream_rows(const unsigned char* X, const uint8_t* y,
-                                                int64_t r0, int64_t r1, rtype* rbuf) {
+                                                int64_t r0, int64_t r1, rtype* rbuf,
+                                                int nact = NB) {
         Tile ta, tb;
         load(ta, X, y, r0, r1 - r0);
         for (int64_t b = r0; b < r1; b += 2 * BATCH) {
             load(tb, X, y, b + BATCH, r1 - b - BATCH);
-            compute(ta, (uint32_t)min((int64_t)BATCH, r1 - b), rbuf);
+            compute(ta, (uint32_t)min((int64_t)BATCH, r1 - b), rbuf, nact);
             if (b + BATCH >= r1) break;
             load(ta, X, y, b + 2 * BATCH, r1 - b - 2 * BATCH);
-            compute(tb, (uint32_t)min((int64_t)BATCH, r1 - b - BATCH), rbuf);
+            compute(tb, (uint32_t)min((int64_t)BATCH, r1 - b - BATCH), rbuf, nact);
         }
     }
 
@@ -612,6 +618,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
         }
     }
     wt.zero_acc();
+    const int nact = __builtin_amdgcn_readfirstlane(min(p.nb, NB));
 
     __shared__ typename WT::rtype rbuf[WPB][WT::RBUF];
 
@@ -629,15 +636,15 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
         wt.load(ta, p.X, p.y, r, p.N - r);
         for (; r < rend; r += 2 * step) {
             wt.load(tb, p.X, p.y, r + step, p.N - r - step);
-            wt.compute(ta, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r)), rbuf[wave]);
+            wt.compute(ta, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r)), rbuf[wave], nact);
             if (r + step >= rend) break;
             wt.load(ta, p.X, p.y, r + 2 * step, p.N - r - 2 * step);
-            wt.compute(tb, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r - step)), rbuf[wave]);
+            wt.compute(tb, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r - step)), rbuf[wave], nact);
         }
     } else {
         const int64_t r0 = min(p.N, nbatch * gw / tw * BATCH);
         const int64_t r1 = min(p.N, nbatch * (gw + 1) / tw * BATCH);
-        wt.stream_rows(p.X, p.y, r0, r1, rbuf[wave]);
+        wt.stream_rows(p.X, p.y, r0, r1, rbuf[wave], nact);
     }
     wt.wave_totals();
 

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -84,7 +85,8 @@ struct glm_server {
     std::condition_variable cv;
     bool stop = false;
     bool accepting = true;
-    std::deque<Request> queue;
+    std::map<int64_t, std::deque<Request>> pending;   // queued requests per data set
+    size_t queued = 0;
     std::unordered_map<uint64_t, Result> results;
     std::map<int64_t, SDataset> datasets;   // references stay valid as sets are added
     int64_t next_ds = 1;
@@ -225,7 +227,9 @@ bool reap(glm_server* s) {
     return any;
 }
 
-// Starts at most one pass on a free slot; returns true if it did.
+// Starts at most one pass on a free slot; returns true if it did.  The data
+// set whose oldest queued request is oldest goes first (FIFO across data
+// sets); data sets that must wait for memory are skipped.
 bool dispatch(glm_server* s) {
     Slot* sl = nullptr;
     for (Slot& c : s->slots)
@@ -239,40 +243,39 @@ bool dispatch(glm_server* s) {
     int64_t dsid = 0;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->queue.empty()) return false;
-        // oldest request first; data sets that must wait for memory are skipped
-        for (size_t qi = 0; qi < s->queue.size() && !dsp; ++qi) {
-            const int64_t cand = s->queue[qi].ds;
-            SDataset& ds = s->datasets[cand];
+        if (s->queued == 0) return false;
+        std::vector<std::pair<Clock::time_point, int64_t>> heads;
+        for (auto& kv : s->pending)
+            if (!kv.second.empty()) heads.push_back({kv.second.front().t_submit, kv.first});
+        std::sort(heads.begin(), heads.end());
+        for (auto& h : heads) {
+            SDataset& ds = s->datasets[h.second];
             const int a = admit(s, ds);
             if (a < 0) {
                 // fail every queued request of this data set
-                for (auto it = s->queue.begin(); it != s->queue.end();) {
-                    if (it->ds == cand) {
-                        s->results[it->ticket].state = R_FAILED;
-                        s->failed++;
-                        it = s->queue.erase(it);
-                    } else {
-                        ++it;
-                    }
+                auto& q = s->pending[h.second];
+                for (Request& r : q) {
+                    s->results[r.ticket].state = R_FAILED;
+                    s->failed++;
                 }
+                s->queued -= q.size();
+                q.clear();
                 s->cv.notify_all();
                 return true;
             }
             if (a == 0) continue;
             dsp = &ds;
-            dsid = cand;
+            dsid = h.second;
+            break;
         }
         if (!dsp) return false;
         const int NB = dsp->mi.fn ? dsp->mi.NB : 1;
-        for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < NB;) {
-            if (it->ds == dsid) {
-                batch.push_back(std::move(*it));
-                it = s->queue.erase(it);
-            } else {
-                ++it;
-            }
+        auto& q = s->pending[dsid];
+        while (!q.empty() && (int)batch.size() < NB) {
+            batch.push_back(std::move(q.front()));
+            q.pop_front();
         }
+        s->queued -= batch.size();
         dsp->inflight++;
         dsp->last_use = ++s->use_clock;
     }
@@ -346,13 +349,13 @@ void scheduler(glm_server* s) {
         bool busy = false;
         for (Slot& sl : s->slots) busy |= sl.busy;
         std::unique_lock<std::mutex> lk(s->mu);
-        if (s->stop && !busy && (s->queue.empty() || !s->accepting)) break;
+        if (s->stop && !busy && (s->queued == 0 || !s->accepting)) break;
         if (!progress) {
             if (busy)
                 s->cv.wait_for(lk, std::chrono::microseconds(5));
             else
                 s->cv.wait_for(lk, std::chrono::milliseconds(2),
-                               [&] { return s->stop || !s->queue.empty(); });
+                               [&] { return s->stop || s->queued > 0; });
         }
     }
 }
@@ -429,7 +432,7 @@ glm_status glm_server_submit(glm_server* s, glm_dataset_id ds, const double* bet
         auto it = s->datasets.find(ds);
         if (it == s->datasets.end())
             GLM_FAIL(GLM_ENOTFOUND, "glm_server_submit: unknown data set %lld", (long long)ds);
-        if ((int64_t)s->queue.size() >= s->cfg.queue_capacity)
+        if ((int64_t)s->queued >= s->cfg.queue_capacity)
             GLM_FAIL(GLM_EAGAIN, "glm_server_submit: request queue full");
         const int K = it->second.src.K;
         r.beta.assign(beta_host, beta_host + K);
@@ -441,11 +444,80 @@ glm_status glm_server_submit(glm_server* s, glm_dataset_id ds, const double* bet
         r.t_submit = Clock::now();
         s->results[r.ticket] = Result{};
         *ticket = r.ticket;
-        s->queue.push_back(std::move(r));
+        s->pending[ds].push_back(std::move(r));
+        s->queued++;
         s->submitted++;
     }
     s->cv.notify_all();
     return GLM_OK;
+}
+
+glm_status glm_server_submit_many(glm_server* s, int32_t n, const glm_dataset_id* ds,
+                                  const double* const* betas, const double* precs, uint64_t* tickets) {
+    clear_error();
+    if (!s || n < 0 || (n > 0 && (!ds || !betas || !precs || !tickets)))
+        GLM_FAIL(GLM_EINVAL, "glm_server_submit_many: bad argument");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->accepting) GLM_FAIL(GLM_ECANCELLED, "glm_server_submit_many: server is shutting down");
+        if ((int64_t)s->queued + n > s->cfg.queue_capacity)
+            GLM_FAIL(GLM_EAGAIN, "glm_server_submit_many: request queue full");
+        for (int i = 0; i < n; ++i) {
+            auto it = s->datasets.find(ds[i]);
+            if (it == s->datasets.end())
+                GLM_FAIL(GLM_ENOTFOUND, "glm_server_submit_many: unknown data set %lld", (long long)ds[i]);
+            if (!betas[i] || !(precs[i] >= 0.0)) GLM_FAIL(GLM_EINVAL, "glm_server_submit_many: request %d", i);
+        }
+        const Clock::time_point now = Clock::now();
+        for (int i = 0; i < n; ++i) {
+            const int K = s->datasets[ds[i]].src.K;
+            Request r;
+            r.beta.assign(betas[i], betas[i] + K);
+            r.has_mean = false;
+            r.ds = ds[i];
+            r.prec = precs[i];
+            r.ticket = s->next_ticket++;
+            r.t_submit = now;
+            s->results[r.ticket] = Result{};
+            tickets[i] = r.ticket;
+            s->pending[ds[i]].push_back(std::move(r));
+        }
+        s->queued += n;
+        s->submitted += n;
+    }
+    s->cv.notify_all();
+    return GLM_OK;
+}
+
+glm_status glm_server_wait_many(glm_server* s, int32_t n, const uint64_t* tickets, double* f_out) {
+    clear_error();
+    if (!s || n < 0 || (n > 0 && !tickets)) GLM_FAIL(GLM_EINVAL, "glm_server_wait_many: bad argument");
+    glm_status first = GLM_OK;
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (int i = 0; i < n; ++i) {
+        while (true) {
+            auto it = s->results.find(tickets[i]);
+            if (it == s->results.end() || it->second.state != R_PENDING) break;
+            s->cv.wait_for(lk, std::chrono::milliseconds(1));
+        }
+        auto it = s->results.find(tickets[i]);
+        if (it == s->results.end()) {
+            if (first == GLM_OK) {
+                first = GLM_ENOTFOUND;
+                set_error("glm_server_wait_many: unknown ticket %llu", (unsigned long long)tickets[i]);
+            }
+            if (f_out) f_out[i] = NAN;
+            continue;
+        }
+        const int state = it->second.state;
+        if (f_out) f_out[i] = state == R_DONE ? it->second.f : NAN;
+        if (state != R_DONE && first == GLM_OK) {
+            first = state == R_CANCELLED ? GLM_ECANCELLED : GLM_EHIP;
+            set_error("glm_server_wait_many: request %d did not finish", i);
+        }
+        s->results.erase(it);
+    }
+    return first;
 }
 
 static glm_status take_result(glm_server* s, uint64_t ticket, double* f, double* g_host) {
@@ -500,7 +572,7 @@ glm_status glm_server_stats(glm_server* s, glm_server_metrics* out) {
     int nres = 0;
     for (auto& kv : s->datasets) nres += kv.second.resident;
     out->resident_datasets = nres;
-    out->queue_depth = (int32_t)s->queue.size();
+    out->queue_depth = (int32_t)s->queued;
     for (int i = 0; i < 9; ++i) out->pass_width_hist[i] = s->hist[i];
     if (!s->lat_us.empty()) {
         std::vector<float> v = s->lat_us;
@@ -535,11 +607,14 @@ glm_status glm_server_shutdown(glm_server* s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->accepting = false;
-        for (Request& r : s->queue) {
-            s->results[r.ticket].state = R_CANCELLED;
-            s->cancelled++;
+        for (auto& kv : s->pending) {
+            for (Request& r : kv.second) {
+                s->results[r.ticket].state = R_CANCELLED;
+                s->cancelled++;
+            }
+            kv.second.clear();
         }
-        s->queue.clear();
+        s->queued = 0;
         s->stop = true;
     }
     s->cv.notify_all();

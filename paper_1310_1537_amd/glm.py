@@ -94,6 +94,8 @@ _SIGS = {
     "glm_server_create": [_P, ctypes.POINTER(glm_server_config), _PP],
     "glm_server_add_dataset": [_P, ctypes.POINTER(glm_dataset_desc), _I32, ctypes.POINTER(_I64)],
     "glm_server_submit": [_P, _I64, _P, _D, _P, ctypes.POINTER(ctypes.c_uint64)],
+    "glm_server_submit_many": [_P, _I32, _P, _P, _P, _P],
+    "glm_server_wait_many": [_P, _I32, _P, _P],
     "glm_server_poll": [_P, ctypes.c_uint64, ctypes.POINTER(_D), _P],
     "glm_server_wait": [_P, ctypes.c_uint64, ctypes.POINTER(_D), _P],
     "glm_server_stats": [_P, ctypes.c_void_p],
@@ -289,6 +291,30 @@ def glm_server_submit(srv: int, ds: int, beta_host, prec: float, mean_host=None)
                                   None if m is None else m.ctypes.data_as(ctypes.c_void_p),
                                   ctypes.byref(t)))
     return t.value
+
+
+def glm_server_submit_many(srv: int, ds_ids, beta_ptrs, precs):
+    """ds_ids: int64 array, beta_ptrs: uint64 array of host addresses of
+    float64 K-vectors (kept alive by the caller), precs: float64 array.
+    Returns the uint64 ticket array."""
+    import numpy as np
+    ds_ids = np.ascontiguousarray(ds_ids, np.int64)
+    beta_ptrs = np.ascontiguousarray(beta_ptrs, np.uint64)
+    precs = np.ascontiguousarray(precs, np.float64)
+    n = len(ds_ids)
+    t = np.empty(n, np.uint64)
+    _check(_lib.glm_server_submit_many(srv, n, ds_ids.ctypes.data, beta_ptrs.ctypes.data,
+                                       precs.ctypes.data, t.ctypes.data))
+    return t
+
+
+def glm_server_wait_many(srv: int, tickets, f_out=None) -> int:
+    """Waits for and retires the tickets; returns the status (errors are not
+    raised so that every ticket is retired)."""
+    import numpy as np
+    tickets = np.ascontiguousarray(tickets, np.uint64)
+    return _lib.glm_server_wait_many(srv, len(tickets), tickets.ctypes.data,
+                                     None if f_out is None else f_out.ctypes.data)
 
 
 def glm_server_poll(srv: int, ticket: int, g_host=None):
