@@ -124,6 +124,10 @@ def bench_plain_big(args):
     bytes_alg = float(N) * K * 4 + N          # X read once + y bytes
     achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
 
+    # measured ceiling: a plain streaming read of the same X buffer
+    ceiling = max(glm.glm_probe_read_bandwidth(ctx, X, blocks_per_cu=b, iters=10)
+                  for b in (1, 2, 4))
+
     # host round-trip latency (beta H2D, launch, f/g D2H, sync), paper Sec. 4.5
     g_host = np.empty(K)
     lat = []
@@ -154,7 +158,8 @@ def bench_plain_big(args):
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS,
                      "traffic": measured_traffic(bytes_alg),
                      "kernel": "fg_fused<f32, 64 lanes/row>", "bytes_per_launch": bytes_alg,
-                     "launch_us_avg": avg_ms * 1e3},
+                     "launch_us_avg": avg_ms * 1e3,
+                     "read_ceiling_GBps": ceiling, "frac_of_read_ceiling": achieved / ceiling},
         "latency_us": {"kernel_p50": float(np.percentile(kern_ms, 50) * 1e3),
                        "kernel_p99": float(np.percentile(kern_ms, 99) * 1e3),
                        "host_call_p50": float(np.percentile(lat_us, 50)),
@@ -175,6 +180,49 @@ def bench_plain_big(args):
     glm.glm_dataset_unregister(ctx, ds)
     glm.glm_destroy(ctx)
     return result
+
+
+def _rel_err(out, ref):
+    import numpy as np
+    return {"f_rel": abs(out[0] - ref[0]) / abs(ref[0]),
+            "g_rel_norm": float(np.linalg.norm(out[1:] - ref[1]) / np.linalg.norm(ref[1]))}
+
+
+def _precision_cpu_leg(w, Xb_dev, Xq_dev, sc_dev):
+    """CPU-baseline leg of the storage-precision workload: times one
+    single-threaded oracle evaluation on the FP32 X, and evaluates the oracle
+    on its own BF16 / FP8 codes of the same X (encoded in row blocks on host
+    threads) for the error report.  The GPU encoders' codes are compared with
+    the oracle's, never handed to it."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    b0 = w.betas[0]
+    t0 = time.perf_counter()
+    refs = {"fp32": oracle.logpost_grad(w.X, w.y, b0, w.prec)}
+    seconds = time.perf_counter() - t0
+    N = w.X.shape[0]
+    edges = np.linspace(0, N, 65).astype(np.int64)
+    blocks = [(int(a), int(b)) for a, b in zip(edges[:-1], edges[1:]) if b > a]
+    s8 = oracle.fp8_col_scales(w.X)
+    Qb = np.empty(w.X.shape, np.uint16)
+    Q8 = np.empty(w.X.shape, np.uint8)
+
+    def enc(ab):
+        a, b = ab
+        Qb[a:b] = oracle.quantize_bf16(w.X[a:b])
+        Q8[a:b] = oracle.quantize_fp8(w.X[a:b], s8)[0]
+
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        list(ex.map(enc, blocks))
+    codes_equal = {"bf16": bool(np.array_equal(Xb_dev.cpu().numpy(), Qb)),
+                   "fp8": bool(np.array_equal(Xq_dev.cpu().numpy(), Q8)
+                               and np.array_equal(sc_dev.cpu().numpy(), s8))}
+    refs["bf16"] = oracle.logpost_grad(Qb, w.y, b0, w.prec, dtype="bf16")
+    refs["fp8"] = oracle.logpost_grad(Q8, w.y, b0, w.prec, dtype="fp8", scale=s8)
+    return {"seconds": seconds, "refs": refs, "codes_equal": codes_equal}
 
 
 def bench_precision(args):
@@ -224,26 +272,13 @@ def bench_precision(args):
         print(f"[bench] {name}: {formats[name]['evals_per_s']:.1f} evals/s "
               f"{formats[name]['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        import oracle
-        b0 = w.betas[0]
-        t0 = time.perf_counter()
-        f32o = oracle.logpost_grad(w.X, w.y, b0, w.prec)
-        dt_cpu = time.perf_counter() - t0
-        qb = Xb.cpu().numpy()
-        bfo = oracle.logpost_grad(qb, w.y, b0, w.prec, dtype="bf16")
-        del qb
-        qq, scn = Xq.cpu().numpy(), sc.cpu().numpy()
-        f8o = oracle.logpost_grad(qq, w.y, b0, w.prec, dtype="fp8", scale=scn)
-        del qq
-
-        def err(out, ref):
-            return {"f_rel": abs(out[0] - ref[0]) / abs(ref[0]),
-                    "g_rel_norm": float(np.linalg.norm(out[1:] - ref[1]) / np.linalg.norm(ref[1]))}
-        formats["fp32"]["kernel_err"] = err(formats["fp32"]["first_out"], f32o)
-        formats["bf16"]["kernel_err"] = err(formats["bf16"]["first_out"], bfo)
-        formats["bf16"]["storage_err"] = err(formats["bf16"]["first_out"], f32o)
-        formats["fp8"]["kernel_err"] = err(formats["fp8"]["first_out"], f8o)
-        formats["fp8"]["storage_err"] = err(formats["fp8"]["first_out"], f32o)
+        cpu = _precision_cpu_leg(w, Xb, Xq, sc)
+        for name in ("fp32", "bf16", "fp8"):
+            out = formats[name]["first_out"]
+            formats[name]["kernel_err"] = _rel_err(out, cpu["refs"][name])
+            if name != "fp32":
+                formats[name]["storage_err"] = _rel_err(out, cpu["refs"]["fp32"])
+                formats[name]["encoder_codes_equal_oracle"] = cpu["codes_equal"][name]
     for f in formats.values():
         f.pop("first_out")
     glm.glm_destroy(ctx)
@@ -260,7 +295,7 @@ def bench_precision(args):
         "formats": formats,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = {"value": 1.0 / dt_cpu, "unit": "evals/s", "cores": 1,
+        result["cpu_baseline"] = {"value": 1.0 / cpu["seconds"], "unit": "evals/s", "cores": 1,
                                   "kind": "oracle", "sample": "one FP32 evaluation at the "
                                   "first trajectory point, single-threaded FP64 C"}
     return result

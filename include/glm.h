@@ -84,8 +84,12 @@ typedef int64_t glm_dataset_id;
  *              must be NULL for the other dtypes
  *   y          device, N bytes, each 0 or 1 (other values: result undefined)
  *   N          rows, N >= 0 (N == 0 evaluates the prior alone)
- *   K          columns, 1 <= K <= GLM_K_MAX
- * X must be aligned to its element size. */
+ *   K          columns, 1 <= K <= GLM_K_MAX and K * sizeof(dtype) <= 4096
+ *              bytes (F64 512, F32 1024, BF16 2048, FP8 4096 columns)
+ * The kernels read rows as 16-byte chunks, so rows must start on 16-byte
+ * boundaries: X 16-byte aligned and ldx * sizeof(dtype) a multiple of 16
+ * (glm_dataset_register rejects other layouts with GLM_EINVAL).  K itself is
+ * free: columns K .. ldx-1 may hold anything and are never used. */
 typedef struct {
     const void* X;
     int64_t ldx;
@@ -127,8 +131,9 @@ const char* glm_last_error(void);
 /* Validates desc, picks the launch plan (kernel instance from dtype, K and
  * alignment; grid size from the device's compute-unit count and the tuning
  * cache) and returns an id.  The data are not read here.  Errors: GLM_EINVAL
- * (N < 0, K out of range, ldx < K, NULL/misaligned X or y with N > 0,
- * col_scale missing for FP8 or present otherwise), GLM_EDTYPE. */
+ * (N < 0, K out of range, ldx < K, NULL X or y with N > 0, X not 16-byte
+ * aligned or ldx * sizeof(dtype) not a multiple of 16, col_scale missing
+ * for FP8 or present otherwise), GLM_EDTYPE. */
 glm_status glm_dataset_register(glm_ctx* ctx, const glm_dataset_desc* desc,
                                 glm_dataset_id* out);
 
@@ -327,6 +332,17 @@ glm_status glm_server_destroy(glm_server* srv);
  * floor of any host-driven evaluation (glm_logpost_grad_host).  Errors:
  * GLM_EINVAL (K < 1, iters < 1, NULL us), GLM_EHIP. */
 glm_status glm_probe_roundtrip(glm_ctx* ctx, int32_t K, int32_t iters, double* us);
+
+/* The measured read ceiling that the fused kernels' bandwidth is compared
+ * with: a plain streaming read of `bytes` (rounded down to 16) at device
+ * address buf (16-byte aligned, caller-owned, only read), by
+ * num_CU * blocks_per_cu blocks of 256 lanes with 16-byte nontemporal loads.
+ * One untimed pass, then `iters` passes timed with events on the context's
+ * stream; writes the achieved GB/s (1e9 bytes/s) to *gbps.  Blocks until done.
+ * Errors: GLM_EINVAL (NULL, bytes < 16, misaligned, blocks_per_cu outside
+ * [1, 16], iters < 1), GLM_ENOMEM, GLM_EHIP. */
+glm_status glm_probe_read_bandwidth(glm_ctx* ctx, const void* buf, int64_t bytes,
+                                    int32_t blocks_per_cu, int32_t iters, double* gbps);
 
 /* ----------------------------------------------------- storage conversions */
 

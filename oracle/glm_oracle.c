@@ -224,14 +224,14 @@ int orc_quantize_bf16(const float* X, int64_t N, int K, int64_t ldx,
 
 int orc_fp8_col_scales(const float* X, int64_t N, int K, int64_t ldx, float* scale) {
     if (K < 1 || N < 0 || ldx < K) return -1;
-    for (int k = 0; k < K; ++k) {
-        float amax = 0.0f;
-        for (int64_t n = 0; n < N; ++n) {
+    /* scale[] first holds the running column maxima (rows in storage order) */
+    for (int k = 0; k < K; ++k) scale[k] = 0.0f;
+    for (int64_t n = 0; n < N; ++n)
+        for (int k = 0; k < K; ++k) {
             float a = fabsf(X[n * ldx + k]);
-            if (a > amax) amax = a;
+            if (a > scale[k]) scale[k] = a;
         }
-        scale[k] = amax > 0.0f ? amax / 448.0f : 1.0f;
-    }
+    for (int k = 0; k < K; ++k) scale[k] = scale[k] > 0.0f ? scale[k] / 448.0f : 1.0f;
     return 0;
 }
 

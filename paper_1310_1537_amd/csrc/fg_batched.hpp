@@ -98,7 +98,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
     };
 
     BatchItem citem{0, 0, 0, -1};   // item being computed
-    auto compute = [&](const Tile& t, const Meta& m) {
+    auto compute = [&](Tile& t, const Meta& m) {
         if (m.first) {
             citem = p.items[m.it];
             wt.set_beta(0, p.betas + (int64_t)citem.group * K, p.scale);
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
             for (int i = 0; i < CPL; ++i)
 #pragma unroll
                 for (int e = 0; e < VE; ++e)
-                    if (wt.col_ok(i)) {
+                    if (wt.elem_ok(i, e)) {
                         const int k = wt.col(i, e);
                         double v = wt.g64[0][i][e];
                         if constexpr (DT == DT_FP8) v *= (double)p.scale[k];

@@ -357,7 +357,9 @@ struct WaveTile {
         unsigned yb[OWN];
     };
 
-    int lane, seg, cl, NC;
+    int lane, seg, cl, NC, KC;
+    bool ragged;             // K * ES is not a whole number of chunks (wave-uniform)
+    u32x4 xmask[CPL];        // bytes of chunk i that are columns < K (ragged K only)
     uint32_t ldb;            // row stride in bytes
     uint32_t loff[CPL];      // byte offset of this lane's chunk i in row slot 0
     uint32_t yoff[OWN];      // row slot (within a batch) of each owned row
@@ -371,12 +373,23 @@ struct WaveTile {
         lane = lane_;
         seg = lane / LPR;
         cl = lane % LPR;
-        NC = K / VE;
+        // A row of K columns spans NC chunks; when K * ES is not a multiple
+        // of 16 the last one is partial and the bytes past column K (row
+        // padding up to ldx, whatever it holds) are cleared before use.
+        NC = (K + VE - 1) / VE;
+        KC = K;
+        ragged = (K % VE) != 0;
         ldb = (uint32_t)(ldx * ES);
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
             const int c = cl + i * LPR;
             loff[i] = c < NC ? (uint32_t)seg * ldb + (uint32_t)c * 16u : 0x80000000u;
+            const int vb = min(16, max(0, K * ES - c * 16));   // valid bytes of chunk i
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int nbq = min(4, max(0, vb - 4 * q));
+                xmask[i][q] = nbq >= 4 ? 0xFFFFFFFFu : ((1u << (8 * nbq)) - 1u);
+            }
         }
 #pragma unroll
         for (int o = 0; o < OWN; ++o) {
@@ -389,6 +402,7 @@ struct WaveTile {
     // Column k of this lane's chunk i, element e.
     __device__ __forceinline__ int col(int i, int e) const { return (cl + i * LPR) * VE + e; }
     __device__ __forceinline__ bool col_ok(int i) const { return cl + i * LPR < NC; }
+    __device__ __forceinline__ bool elem_ok(int i, int e) const { return col(i, e) < KC; }
 
     // Coefficient vector of slot b (K doubles); FP8 folds the column scales in.
     __device__ __forceinline__ void set_beta(int b, const double* beta, const float* scale) {
@@ -397,7 +411,7 @@ struct WaveTile {
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
                 double v = 0.0;
-                if (col_ok(i)) {
+                if (elem_ok(i, e)) {
                     v = beta[col(i, e)];
                     if constexpr (DT == DT_FP8) v *= (double)scale[col(i, e)];
                 }
@@ -455,8 +469,14 @@ struct WaveTile {
     // g of the first nact slots (nact is wave-uniform; the other slots are
     // skipped, so a partly filled pass costs what it carries).  rbuf: this
     // wave's LDS slice of RBUF values.
-    __device__ __forceinline__ void compute(const Tile& t, uint32_t nvalid, rtype* rbuf,
+    __device__ __forceinline__ void compute(Tile& t, uint32_t nvalid, rtype* rbuf,
                                             int nact = NB) {
+        if (ragged) {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int i = 0; i < CPL; ++i) t.x[j][i] &= xmask[i];
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             if (b >= nact) break;

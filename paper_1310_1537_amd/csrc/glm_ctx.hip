@@ -224,6 +224,67 @@ glm_status glm_probe_roundtrip(glm_ctx* ctx, int32_t K, int32_t iters, double* u
     return GLM_OK;
 }
 
+// Pure streaming read: every lane reads 16-byte words at a grid stride with
+// eight loads in flight and folds them into a register; a lane writes its fold
+// only in the (data-dependent, practically never taken) all-ones case, which
+// keeps the loads alive without adding traffic.
+typedef unsigned int probe_u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_read_probe(const probe_u32x4* __restrict__ p, int64_t n,
+                                                    unsigned* __restrict__ sink) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    probe_u32x4 acc = {0u, 0u, 0u, 0u};
+    for (; i + 7 * stride < n; i += 8 * stride) {
+        probe_u32x4 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = __builtin_nontemporal_load(p + i + j * stride);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc ^= v[j];
+    }
+    for (; i < n; i += stride) acc ^= __builtin_nontemporal_load(p + i);
+    if ((acc.x & acc.y & acc.z & acc.w) == 0xFFFFFFFFu)
+        sink[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc.x ^ acc.y;
+}
+
+glm_status glm_probe_read_bandwidth(glm_ctx* ctx, const void* buf, int64_t bytes,
+                                    int32_t blocks_per_cu, int32_t iters, double* gbps) {
+    clear_error();
+    if (!ctx || !buf || !gbps || bytes < 16 || blocks_per_cu < 1 || blocks_per_cu > 16 || iters < 1)
+        GLM_FAIL(GLM_EINVAL, "glm_probe_read_bandwidth: bad argument");
+    if ((uintptr_t)buf % 16) GLM_FAIL(GLM_EINVAL, "glm_probe_read_bandwidth: buffer not 16-byte aligned");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    const int blocks = ctx->num_cu * blocks_per_cu;
+    const int64_t n = bytes / 16;
+    unsigned* sink = nullptr;
+    if (hipMalloc((void**)&sink, (size_t)blocks * 256 * sizeof(unsigned)) != hipSuccess)
+        GLM_FAIL(GLM_ENOMEM, "glm_probe_read_bandwidth: device allocation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    hipStream_t s = ctx->own_stream;
+    // one untimed pass, then iters timed passes
+    for (int it = -1; it < iters && e == hipSuccess; ++it) {
+        if (it == 0) e = hipEventRecord(e0, s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_read_probe, dim3(blocks), dim3(256), 0, s,
+                           (const probe_u32x4*)buf, n, sink);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    if (e != hipSuccess) GLM_FAIL(GLM_EHIP, "glm_probe_read_bandwidth: %s", hipGetErrorString(e));
+    *gbps = (double)n * 16.0 * iters / (ms * 1e-3) / 1e9;
+    return GLM_OK;
+}
+
 glm_status glm_dataset_unregister(glm_ctx* ctx, glm_dataset_id id) {
     clear_error();
     if (!ctx) GLM_FAIL(GLM_EINVAL, "glm_dataset_unregister: ctx is NULL");

@@ -66,17 +66,16 @@ int pow2ceil(int v) {
 glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
     const int es = elem_size(d.dtype);
     const int ve = 16 / es;
-    const bool vec_ok = (d.K * es) % 16 == 0 && (d.ldx * es) % 16 == 0 &&
-                        ((uintptr_t)d.X % 16) == 0;
+    const bool vec_ok = (d.ldx * es) % 16 == 0 && ((uintptr_t)d.X % 16) == 0;
     if (!vec_ok)
         GLM_FAIL(GLM_EINVAL,
-                 "plan: rows must be whole 16-byte chunks (K*%d and ldx*%d multiples of 16, X "
+                 "plan: rows must start on 16-byte boundaries (ldx*%d a multiple of 16, X "
                  "16-byte aligned)",
-                 es, es);
+                 es);
     if (d.ldx * es > (1 << 21))
         GLM_FAIL(GLM_EINVAL, "plan: row stride ldx*%d = %lld bytes exceeds 2 MiB", es,
                  (long long)(d.ldx * es));
-    const int nc = d.K / ve;
+    const int nc = (d.K + ve - 1) / ve;   // chunks per row, the last possibly partial
     Plan p;
     p.kind = 0;
     p.lpr = std::min(64, pow2ceil(nc));

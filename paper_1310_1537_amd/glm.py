@@ -103,6 +103,7 @@ _SIGS = {
     "glm_server_shutdown": [_P],
     "glm_server_destroy": [_P],
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
+    "glm_probe_read_bandwidth": [_P, _P, _I64, _I32, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
     "glm_fp8_col_scales": [_P, _P, _I64, _I32, _I64, _P, _P],
     "glm_quantize_fp8": [_P, _P, _I64, _I32, _I64, _P, _P, _I64, _P],
@@ -185,6 +186,22 @@ def make_desc(X, y, N=None, K=None, ldx=None, dtype=None, col_scale=None) -> glm
             ldx = X.stride(0) if ldx is None else ldx
         dtype = _dtype_code(X, dtype)
     return glm_dataset_desc(_ptr(X), ldx, dtype, _ptr(col_scale), _ptr(y), N, K)
+
+
+def aligned_rows(X):
+    """A copy of the 2-D device tensor X whose rows start on 16-byte
+    boundaries (leading dimension rounded up, padding zero), returned as the
+    N x K view the data-set descriptor takes; X itself when already aligned.
+    The caller keeps the returned view alive while the data set is in use."""
+    es = X.element_size()
+    step = max(1, 16 // es)
+    N, K = X.shape
+    if X.stride(1) == 1 and (X.stride(0) * es) % 16 == 0 and X.data_ptr() % 16 == 0:
+        return X
+    ld = (K + step - 1) // step * step
+    buf = torch.zeros((N, ld), dtype=X.dtype, device=X.device)
+    buf[:, :K] = X
+    return buf[:, :K]
 
 
 def glm_dataset_register(ctx: int, desc: glm_dataset_desc) -> int:
@@ -359,6 +376,18 @@ def glm_probe_roundtrip(ctx: int, K: int, iters: int = 1000) -> float:
 
 
 # ---------------------------------------------------------------- conversions
+
+def glm_probe_read_bandwidth(ctx: int, buf, nbytes: int | None = None, blocks_per_cu: int = 2,
+                             iters: int = 10) -> float:
+    """GB/s of a plain streaming read of a device buffer (a torch tensor or
+    a device address with nbytes)."""
+    if nbytes is None:
+        nbytes = buf.numel() * buf.element_size()
+    gb = ctypes.c_double()
+    _check(_lib.glm_probe_read_bandwidth(ctx, _ptr(buf), int(nbytes), blocks_per_cu, iters,
+                                         ctypes.byref(gb)))
+    return gb.value
+
 
 def glm_quantize_bf16(ctx: int, X, Q, stream=None) -> None:
     N, K = X.shape

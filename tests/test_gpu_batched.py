@@ -152,3 +152,22 @@ def test_hierarchical_workload_full_size(ctx):
     (got,), info = _run(ctx, w.X, w.y, w.offsets, w.betas, w.prec, mean=w.mu, tune=True)
     print("hierarchical schedule:", info, flush=True)
     _check_groups(got, w.X.astype(np.float64), w.y, w.offsets, w.betas, w.prec, mean=w.mu)
+
+
+@pytest.mark.parametrize("K", [3, 13, 37])
+def test_ragged_k_groups(ctx, K):
+    """Group rows whose K is not a whole number of 16-byte chunks, padding
+    NaN: split and whole groups both ignore the padding."""
+    X, y, off, B = _groups(SIZES, K, 40 + K)
+    step = 4
+    ld = (K + step - 1) // step * step + step
+    buf = np.full((X.shape[0], ld), np.nan, np.float32)
+    buf[:, :K] = X
+    Xd = torch.from_numpy(buf).to(DEV)[:, :K]
+    yd = to_dev(y)
+    gs = glm.glm_groupset_create(ctx, glm.make_desc(Xd, yd), off, tune=False)
+    out = torch.full((len(SIZES), K + 1), float("nan"), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_batched(ctx, gs, to_dev(B), glm.make_prior(1.0), out)
+    torch.cuda.synchronize()
+    glm.glm_groupset_destroy(gs)
+    _check_groups(out.cpu().numpy(), X.astype(np.float64), y, off, B, 1.0)

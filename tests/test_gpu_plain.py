@@ -174,3 +174,85 @@ def test_big_plain_workload_full_size(ctx):
         print(f"big plain point {i}: rel err f {ef:.2e}  g {eg:.2e}", flush=True)
         assert ef <= 1e-9 and eg <= 1e-7, (ef, eg)
     glm.glm_dataset_unregister(ctx, ds)
+
+
+def test_read_probe(ctx):
+    """The streaming-read probe runs and reports a plausible rate; bad
+    arguments are rejected before any launch."""
+    buf = torch.empty(64 << 20, dtype=torch.uint8, device=DEV)
+    gb = glm.glm_probe_read_bandwidth(ctx, buf, blocks_per_cu=2, iters=3)
+    assert 10.0 < gb < 20_000.0
+    for bad in (dict(nbytes=8), dict(blocks_per_cu=0), dict(iters=0)):
+        kw = dict(nbytes=None, blocks_per_cu=2, iters=1)
+        kw.update(bad)
+        with pytest.raises(glm.GlmError) as e:
+            glm.glm_probe_read_bandwidth(ctx, buf, **kw)
+        assert e.value.status == glm.GLM_EINVAL
+
+
+def _nan_padded(X):
+    """Device copy of X with a 16-byte-aligned leading dimension whose padding
+    columns hold NaN (FP32/FP64) or all-ones codes (NaN in BF16 and E4M3FN):
+    the kernels must never use them."""
+    X = np.ascontiguousarray(X)
+    step = 16 // X.itemsize
+    N, K = X.shape
+    ld = (K + step - 1) // step * step + step
+    fill = np.nan if X.dtype.kind == "f" else np.iinfo(X.dtype).max
+    buf = np.full((N, ld), fill, dtype=X.dtype)
+    buf[:, :K] = X
+    return torch.from_numpy(buf).to(DEV)[:, :K]
+
+
+@pytest.mark.parametrize("K", [1, 3, 5, 10, 50, 255, 1021])
+@pytest.mark.parametrize("N", [1, 257, 30_011])
+def test_ragged_k_f32_with_nan_padding(ctx, K, N):
+    """K not a multiple of the 16-byte chunk: the last chunk of every row is
+    partial and the padding (NaN here) is cleared before use."""
+    g_ = np.random.default_rng(K * 7 + N)
+    X = g_.standard_normal((N, K)).astype(np.float32)
+    y = (g_.random(N) < 0.5).astype(np.uint8)
+    beta = g_.standard_normal(K) / math.sqrt(K)
+    Xd = _nan_padded(X)
+    assert Xd.stride(0) != K
+    f, g = eval_gpu(ctx, Xd, to_dev(y), beta, 0.01)
+    check_against_oracle(f, g, X.astype(np.float64), y, beta, 0.01)
+
+
+@pytest.mark.parametrize("K", [1, 7, 21, 333])
+def test_ragged_k_f64_bf16_fp8(ctx, K):
+    N = 5_003
+    g_ = np.random.default_rng(K)
+    X = g_.standard_normal((N, K)).astype(np.float32)
+    y = (g_.random(N) < 0.5).astype(np.uint8)
+    beta = g_.standard_normal(K) / math.sqrt(K)
+    X64 = X.astype(np.float64)
+    f, g = eval_gpu(ctx, _nan_padded(X64), to_dev(y), beta, 0.1)
+    check_against_oracle(f, g, X64, y, beta, 0.1, storage="f64")
+    Qb = oracle.quantize_bf16(X)
+    f, g = eval_gpu(ctx, _nan_padded(Qb), to_dev(y), beta, 0.1, dtype=glm.GLM_BF16)
+    check_against_oracle(f, g, oracle.decode_bf16(Qb), y, beta, 0.1, X_for_oracle=Qb,
+                         oracle_kw={"dtype": "bf16"})
+    Q8, s8 = oracle.quantize_fp8(X)
+    f, g = eval_gpu(ctx, _nan_padded(Q8), to_dev(y), beta, 0.1, dtype=glm.GLM_FP8_E4M3,
+                    scale=to_dev(s8))
+    check_against_oracle(f, g, oracle.decode_fp8(Q8, s8), y, beta, 0.1, X_for_oracle=Q8,
+                         oracle_kw={"dtype": "fp8", "scale": s8})
+
+
+def test_aligned_rows_helper_and_rejection(ctx):
+    """A contiguous K = 10 FP32 matrix (40-byte rows) is rejected; the
+    binding's aligned_rows() copy is accepted and gives the same result."""
+    N, K = 4_001, 10
+    g_ = np.random.default_rng(5)
+    X = g_.standard_normal((N, K)).astype(np.float32)
+    y = (g_.random(N) < 0.5).astype(np.uint8)
+    beta = g_.standard_normal(K)
+    Xd, yd = to_dev(X), to_dev(y)
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
+    assert e.value.status == glm.GLM_EINVAL
+    Xa = glm.aligned_rows(Xd)
+    assert Xa.stride(0) == 12
+    f, g = eval_gpu(ctx, Xa, yd, beta, 0.01)
+    check_against_oracle(f, g, X.astype(np.float64), y, beta, 0.01)

@@ -235,3 +235,21 @@ def test_server_device_resident_and_threads(ctx):
     for beta, f, g in list(res.values())[::10]:
         _check(f, g, X.astype(np.float64), y, beta, 0.01)
     glm.glm_server_destroy(srv)
+
+
+@pytest.mark.parametrize("K", [5, 100])
+def test_multi_ragged_k(ctx, K):
+    X, y, bt = _data(10_007, K, 80 + K)
+    ld = (K + 3) // 4 * 4 + 4
+    buf = np.full((X.shape[0], ld), np.nan, np.float32)
+    buf[:, :K] = X
+    Xd = torch.from_numpy(buf).to(DEV)[:, :K]
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, to_dev(y)))
+    B = _betas(bt, 6, 81)
+    out = torch.empty((6, K + 1), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), 6, glm.make_prior(0.01), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for b in range(6):
+        _check(o[b, 0], o[b, 1:], X.astype(np.float64), y, B[b], 0.01)
+    glm.glm_dataset_unregister(ctx, ds)
