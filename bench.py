@@ -47,18 +47,26 @@ def measured_traffic(bytes_alg: float):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, n_max: int, budget_s: float = 15.0):
+def cpu_baseline(w, n_max: int, budget_s: float = 15.0, family: str = "logistic"):
     """The FP64 oracle (single-threaded C) on the first trajectory points of
     the same workload, until about budget_s seconds have been spent."""
     import oracle
     res = []
     t0 = time.perf_counter()
     for i in range(n_max):
-        res.append(oracle.logpost_grad(w.X, w.y, w.betas[i], w.prec))
+        res.append(oracle.logpost_grad(w.X, w.y, w.betas[i], w.prec, family=family))
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
     return res, dt
+
+
+def _device_hold(torch, seconds: float) -> None:
+    """Queues a spin of about `seconds` on the current stream (torch's
+    cycle-count sleep kernel) when available."""
+    sleep = getattr(torch.cuda, "_sleep", None)
+    if sleep is not None:
+        sleep(int(seconds * 2.4e9))
 
 
 def _timed_evals(glm, lib, ctx, ds, prior, betas, outs, K, warmup, steps, stream):
@@ -92,7 +100,7 @@ def _timed_evals(glm, lib, ctx, ds, prior, betas, outs, K, warmup, steps, stream
     return wall, np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
 
 
-def bench_plain_big(args):
+def bench_plain_big(args, poisson: bool = False):
     import numpy as np
     import torch
 
@@ -101,7 +109,8 @@ def bench_plain_big(args):
 
     dev = torch.device("cuda:0")
     n_traj = 1000
-    w = synth.plain_big(n_evals=n_traj)
+    w = synth.plain_poisson(n_evals=n_traj) if poisson else synth.plain_big(n_evals=n_traj)
+    family = glm.GLM_POISSON if poisson else glm.GLM_LOGISTIC
     N, K = w.X.shape
     print(f"[bench] workload N={N} K={K} fp32; generated", file=sys.stderr, flush=True)
     X = torch.from_numpy(w.X).to(dev)
@@ -113,7 +122,7 @@ def bench_plain_big(args):
     stream = torch.cuda.current_stream()
 
     ctx = glm.glm_create(0)
-    ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y, family=family))
     prior = glm.make_prior(w.prec)
     wall, kern_ms = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K, args.warmup,
                                  args.steps, stream)
@@ -151,12 +160,15 @@ def bench_plain_big(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plain big: Bayesian logistic regression N=4,000,000 K=256, "
-                               "FP32 X (26 binary columns), random-walk beta trajectory",
+        "config": {"workload": ("plain big, Poisson regression (log link): N=4,000,000 K=256, "
+                                "FP32 X (26 binary columns), random-walk beta trajectory"
+                                if poisson else
+                                "plain big: Bayesian logistic regression N=4,000,000 K=256, "
+                                "FP32 X (26 binary columns), random-walk beta trajectory"),
                    "N": N, "K": K, "storage": "fp32", "result": "fp64", "prior_sd": 10},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS,
-                     "traffic": measured_traffic(bytes_alg),
+                     "traffic": None if poisson else measured_traffic(bytes_alg),
                      "kernel": "fg_fused<f32, 64 lanes/row>", "bytes_per_launch": bytes_alg,
                      "launch_us_avg": avg_ms * 1e3,
                      "read_ceiling_GBps": ceiling, "frac_of_read_ceiling": achieved / ceiling},
@@ -167,7 +179,7 @@ def bench_plain_big(args):
     }
 
     if not args.no_cpu_baseline:
-        res, dt = cpu_baseline(w, n_max=30)
+        res, dt = cpu_baseline(w, n_max=30, family="poisson" if poisson else "logistic")
         n = len(res)
         ef = max(abs(out_np[i][0] - res[i][0]) / abs(res[i][0]) for i in range(n))
         eg = max(np.linalg.norm(out_np[i][1:] - res[i][1]) / np.linalg.norm(res[i][1])
@@ -606,9 +618,122 @@ def bench_copy(args):
             "bytes_read": n, "bytes_written": n}
 
 
+def bench_diff(args):
+    """Differential update (paper Sec. 3.4.4) on the 4M x 256 FP32 workload:
+    a column-major copy of X, u = X beta kept on the device, and a sweep over
+    the coordinates: per step, f at nd candidate moves of beta_k (one read of
+    column k, u and y) and a commit of one move (u += delta X_k)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    w = synth.plain_big(n_evals=2)
+    N, K = w.X.shape
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    ctx = glm.glm_create(0)
+    Xt = torch.empty((K, N), dtype=torch.float32, device=dev)
+    glm.glm_transpose(ctx, glm.make_desc(X, y), Xt, N)
+    del X
+    cs = glm.glm_colset_register(ctx, glm.make_colset_desc(Xt, y))
+    beta0 = w.betas[0]
+    bd = torch.from_numpy(beta0.copy()).to(dev)
+    u = torch.empty(N, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    glm.glm_linpred(ctx, cs, bd, u, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    linpred_ms = e0.elapsed_time(e1)
+    prior = glm.make_prior(w.prec)
+    total = args.warmup + args.steps
+    rng = np.random.default_rng(7)
+    res = {}
+    for nd in (1, 8):
+        deltas = torch.from_numpy(rng.normal(0.0, 0.01, (total, nd))).to(dev)
+        outs = torch.empty((total, nd), dtype=torch.float64, device=dev)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for i in range(args.warmup):
+            glm.glm_diff_logpost(ctx, cs, u, bd, i % K, deltas[i], nd, prior, outs[i], stream)
+            glm.glm_diff_commit(ctx, cs, u, bd, i % K, deltas[i, :1], stream)
+        torch.cuda.synchronize()
+        # a short device-side wait first, so that the host has queued the
+        # timed launches before the GPU reaches them (otherwise host call
+        # overhead would sit between the events and the kernels)
+        _device_hold(torch, 20e-3)
+        for j in range(args.steps):
+            i = args.warmup + j
+            a, b, c = ev[j]
+            a.record(stream)
+            glm.glm_diff_logpost(ctx, cs, u, bd, i % K, deltas[i], nd, prior, outs[i], stream)
+            b.record(stream)
+            glm.glm_diff_commit(ctx, cs, u, bd, i % K, deltas[i, :1], stream)
+            c.record(stream)
+        torch.cuda.synchronize()
+        span_s = ev[0][0].elapsed_time(ev[-1][2]) * 1e-3
+        ev_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
+        cm_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+        res[nd] = {"steps_per_s": args.steps / span_s, "eval_us_avg": float(ev_ms.mean() * 1e3),
+                   "eval_us_p50": float(np.percentile(ev_ms, 50) * 1e3),
+                   "commit_us_avg": float(cm_ms.mean() * 1e3),
+                   "f_evals_per_s_kernel": nd / float(ev_ms.mean() * 1e-3)}
+        print(f"[bench] diff nd={nd}: {res[nd]}", file=sys.stderr, flush=True)
+    eval_bytes = float(N) * (4 + 8 + 1)
+    commit_bytes = float(N) * (4 + 8 + 8)
+    r1 = res[1]
+    achieved = eval_bytes / (r1["eval_us_avg"] * 1e-6) / 1e9
+    result = {
+        "metric": "differential-update log-posterior evals/s (one coefficient moved, "
+                  "FP64 result) & HBM GB/s % peak",
+        "value": r1["f_evals_per_s_kernel"], "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 / r1["steps_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "differential update: N=4,000,000 K=256 FP32 X (column-major "
+                               "copy), one coefficient per step, nd candidate moves per pass",
+                   "N": N, "K": K},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
+                     "bytes_per_launch": eval_bytes, "launch_us_avg": r1["eval_us_avg"],
+                     "note": "column k is new each step; u (32 MB) and y (4 MB) are re-read "
+                             "every step and may be served from the 256 MB Infinity Cache"},
+        "by_candidates": {str(k): v for k, v in res.items()},
+        "commit_GBps": commit_bytes / (res[1]["commit_us_avg"] * 1e-6) / 1e9,
+        "linpred_ms": linpred_ms,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        b2 = beta0.copy()
+        t0 = time.perf_counter()
+        fo, _ = oracle.logpost_grad(w.X, w.y, b2, w.prec)
+        dt = time.perf_counter() - t0
+        # the GPU at the same point: u = X beta0, a zero move of coordinate 0
+        bd.copy_(torch.from_numpy(beta0))
+        glm.glm_linpred(ctx, cs, bd, u, stream)
+        z = torch.zeros(1, dtype=torch.float64, device=dev)
+        fo_gpu = torch.empty(1, dtype=torch.float64, device=dev)
+        glm.glm_diff_logpost(ctx, cs, u, bd, 0, z, 1, prior, fo_gpu, stream)
+        torch.cuda.synchronize()
+        result["err_vs_fp64"] = {"f_rel": abs(float(fo_gpu.cpu()[0]) - fo) / abs(fo)}
+        result["cpu_baseline"] = {"value": 1.0 / dt, "unit": "evals/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": "one full FP64 evaluation at the first trajectory "
+                                            "point (the oracle has no differential form), "
+                                            "single-threaded C"}
+    glm.glm_colset_unregister(ctx, cs)
+    glm.glm_destroy(ctx)
+    return result
+
+
 WORKLOADS = {"copy": bench_copy, "plain_big": bench_plain_big, "precision": bench_precision,
              "batched": bench_batched, "plain_small": bench_plain_small,
-             "serving": bench_serving}
+             "serving": bench_serving, "diff": bench_diff,
+             "poisson": lambda a: bench_plain_big(a, poisson=True)}
 
 
 def main() -> int:

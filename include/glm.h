@@ -68,6 +68,18 @@ typedef enum {
     GLM_FP8_E4M3 = 3
 } glm_dtype;
 
+/* Response model (the per-row map; the linear algebra is the same for all,
+ * as the paper notes for GLMs other than the logistic one, Sec. 3.4):
+ *   GLM_LOGISTIC  y in {0, 1}:  t = y u - softplus(u),  r = y - sigmoid(u)
+ *                 (Sec. 3.1.1, eq-loglike-binlogit)
+ *   GLM_POISSON   y in {0 .. 255} (counts, log link):  t = y u - exp(u),
+ *                 r = y - exp(u); the constant -sum_n log(y_n!) is left out
+ * f = sum_n t_n - prior,  g = sum_n r_n x_n - prior gradient. */
+typedef enum {
+    GLM_LOGISTIC = 0,
+    GLM_POISSON = 1
+} glm_family;
+
 /* Largest number of columns K any entry point accepts. */
 #define GLM_K_MAX 4096
 
@@ -75,17 +87,19 @@ typedef struct glm_ctx glm_ctx;
 typedef int64_t glm_dataset_id;
 
 /* A data set: X (N x K, row-major, element (n,k) at X[n*ldx + k]) and the
- * binary response y.  All pointers are device pointers owned by the caller,
+ * response y of the chosen family.  All pointers are device pointers owned by the caller,
  * who keeps them alive and unchanged until the data set is unregistered.
  *   X          device, N*ldx elements of dtype (may be NULL when N == 0)
  *   ldx        leading dimension in elements, ldx >= K
  *   dtype      a glm_dtype
  *   col_scale  device, K FP32 scales s_k (value = code * s_k); FP8_E4M3 only,
  *              must be NULL for the other dtypes
- *   y          device, N bytes, each 0 or 1 (other values: result undefined)
+ *   y          device, N bytes: 0 or 1 for GLM_LOGISTIC (other values:
+ *              result undefined), counts 0..255 for GLM_POISSON
  *   N          rows, N >= 0 (N == 0 evaluates the prior alone)
  *   K          columns, 1 <= K <= GLM_K_MAX and K * sizeof(dtype) <= 4096
  *              bytes (F64 512, F32 1024, BF16 2048, FP8 4096 columns)
+ *   family     a glm_family
  * The kernels read rows as 16-byte chunks, so rows must start on 16-byte
  * boundaries: X 16-byte aligned and ldx * sizeof(dtype) a multiple of 16
  * (glm_dataset_register rejects other layouts with GLM_EINVAL).  K itself is
@@ -98,6 +112,7 @@ typedef struct {
     const uint8_t* y;
     int64_t N;
     int32_t K;
+    int32_t family;   /* a glm_family; 0 (zero-initialised) is logistic */
 } glm_dataset_desc;
 
 /* Gaussian prior N(m, prec^-1 I) on beta (Sec. 3.1.1 leaves it open).
@@ -322,6 +337,69 @@ glm_status glm_server_shutdown(glm_server* srv);
 
 /* Shuts down (if needed) and frees the server and its device copies. */
 glm_status glm_server_destroy(glm_server* srv);
+
+/* ----------------------------------------------- differential update */
+
+/* One-coefficient-at-a-time samplers (slice sampling or Gibbs over the
+ * coordinates of beta) change a single beta_k per step.  With u = X beta kept
+ * on the device, f(beta + delta e_k) needs column k of X, u and y only:
+ * u' = u + delta X_k (Sec. 3.4.4, the differential update).  The calls below
+ * work on a column-major copy of X (a column set) so that column k is one
+ * contiguous stream: N (sizeof(dtype) + 8 + 1) bytes per evaluation instead
+ * of N (K sizeof(dtype) + 1).
+ *
+ * Column set: element (n, k) at Xt[k*ldt + n]; ldt >= N; Xt aligned to its
+ * element; the other fields as in glm_dataset_desc.  All pointers are device
+ * pointers owned by the caller and kept alive until unregistered. */
+typedef struct {
+    const void* Xt;
+    int64_t ldt;
+    int32_t dtype;
+    const float* col_scale;
+    const uint8_t* y;
+    int64_t N;
+    int32_t K;
+    int32_t family;
+} glm_colset_desc;
+
+/* Writes the column-major copy of a row-major data set's X into Xt (device,
+ * K*ldt elements of the same dtype, caller-owned; ldt >= N), bit for bit.
+ * Async on `stream`.  Errors: GLM_EINVAL (as glm_dataset_register, or
+ * ldt < N, Xt NULL/misaligned), GLM_EDTYPE, GLM_EHIP. */
+glm_status glm_transpose(glm_ctx* ctx, const glm_dataset_desc* rows, void* Xt, int64_t ldt,
+                         void* stream);
+
+/* Registers a column set (FP8: the K scales are read once, here).  Errors:
+ * GLM_EINVAL (N < 0, K out of range, ldt < N, NULL/misaligned Xt or y with
+ * N > 0, col_scale missing for FP8 or present otherwise), GLM_EDTYPE,
+ * GLM_EHIP. */
+glm_status glm_colset_register(glm_ctx* ctx, const glm_colset_desc* desc, glm_dataset_id* out);
+glm_status glm_colset_unregister(glm_ctx* ctx, glm_dataset_id id);
+
+/* u = X beta (device: beta K doubles in, u N doubles out), FP64 products
+ * and sums in column order.  Async.  Errors: GLM_EINVAL, GLM_ENOTFOUND,
+ * GLM_EHIP. */
+glm_status glm_linpred(glm_ctx* ctx, glm_dataset_id colset, const double* beta, double* u,
+                       void* stream);
+
+/* f(beta + delta_j e_k) for j < nd (Sec. 3.4.4 with the log-posterior of
+ * Sec. 3.1.1): device u = X beta (N doubles), beta (K doubles), deltas (nd
+ * doubles) and f_out (nd doubles).  Each pass reads column k, u and y once
+ * for up to 16 step sizes.  Per-row terms and all sums in FP64; the prior is
+ * evaluated at beta + delta_j e_k.  Async; bitwise reproducible.  Errors:
+ * GLM_EINVAL (NULL, nd < 1, k outside [0, K), prec < 0), GLM_ENOTFOUND,
+ * GLM_ENOMEM, GLM_EHIP. */
+glm_status glm_diff_logpost(glm_ctx* ctx, glm_dataset_id colset, const double* u,
+                            const double* beta, int32_t k, const double* deltas, int32_t nd,
+                            const glm_prior* prior, double* f_out, void* stream);
+
+/* Commits a step: u += delta X_k and, when beta is not NULL, beta_k += delta
+ * (device pointers; delta is one device double, so a device-side sampler can
+ * produce it without a host round trip).  The new u equals, bit for bit, the
+ * u' that glm_diff_logpost evaluated for the same delta.  Async.  Errors:
+ * GLM_EINVAL, GLM_ENOTFOUND, GLM_EHIP. */
+glm_status glm_diff_commit(glm_ctx* ctx, glm_dataset_id colset, double* u, double* beta,
+                           int32_t k, const double* delta, void* stream);
 
 /* -------------------------------------------------------- boundary probe */
 

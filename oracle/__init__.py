@@ -26,6 +26,7 @@ SRC = os.path.join(HERE, "glm_oracle.c")
 LIB = os.path.join(HERE, "libglm_oracle.so")
 
 F64, F32, BF16, FP8 = 0, 1, 2, 3
+FAMILIES = {"logistic": 0, "poisson": 1}
 _DT = {np.dtype(np.float64): F64, np.dtype(np.float32): F32}
 
 
@@ -49,9 +50,10 @@ def lib():
             build()
         L = ctypes.CDLL(LIB)
         P, I64, I, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
-        L.orc_logpost_grad.argtypes = [P, I, I64, P, P, I64, I, P, D, P, P]
-        L.orc_logpost_grad_multi.argtypes = [P, I, I64, P, P, I64, I, P, I, D, P, P]
-        L.orc_logpost_grad_groups.argtypes = [P, I, I64, P, P, P, I, I, P, D, P, I, P]
+        L.orc_logpost_grad.argtypes = [P, I, I64, P, P, I64, I, P, D, P, I, P]
+        L.orc_logpost_grad_multi.argtypes = [P, I, I64, P, P, I64, I, P, I, D, P, I, P]
+        L.orc_linpred.argtypes = [P, I, I64, P, I64, I, P, P]
+        L.orc_logpost_grad_groups.argtypes = [P, I, I64, P, P, P, I, I, P, D, P, I, I, P]
         L.orc_quantize_bf16.argtypes = [P, I64, I, I64, P, I64]
         L.orc_fp8_col_scales.argtypes = [P, I64, I, I64, P]
         L.orc_quantize_fp8.argtypes = [P, I64, I, I64, P, P, I64]
@@ -89,9 +91,10 @@ def _xinfo(X, dtype):
     return code, X.strides[0] // X.itemsize, X
 
 
-def logpost_grad(X, y, beta, prec, mean=None, dtype=None, scale=None):
+def logpost_grad(X, y, beta, prec, mean=None, dtype=None, scale=None, family="logistic"):
     """f and g at one beta.  X: float64/float32 array, or uint16 (dtype='bf16')
-    / uint8 (dtype='fp8' with FP32 column scales) codes.  Returns (f, g)."""
+    / uint8 (dtype='fp8' with FP32 column scales) codes; family 'logistic'
+    (y in {0, 1}) or 'poisson' (y counts).  Returns (f, g)."""
     code, ldx, X = _xinfo(X, dtype)
     N, K = X.shape
     y = np.ascontiguousarray(y, np.uint8)
@@ -101,13 +104,25 @@ def logpost_grad(X, y, beta, prec, mean=None, dtype=None, scale=None):
     scale = None if scale is None else np.ascontiguousarray(scale, np.float32)
     out = np.empty(1 + K)
     rc = lib().orc_logpost_grad(_p(X), code, ldx, _p(scale), _p(y), N, K, _p(beta),
-                                float(prec), _p(mean), _p(out))
+                                float(prec), _p(mean), FAMILIES[family], _p(out))
     if rc:
         raise ValueError("oracle rejected its arguments")
     return out[0], out[1:].copy()
 
 
-def logpost_grad_multi(X, y, betas, prec, means=None, dtype=None, scale=None):
+def linpred(X, beta, dtype=None, scale=None):
+    """u = X beta in FP64 (k order) for every row."""
+    code, ldx, X = _xinfo(X, dtype)
+    N, K = X.shape
+    beta = np.ascontiguousarray(beta, np.float64)
+    scale = None if scale is None else np.ascontiguousarray(scale, np.float32)
+    u = np.empty(N)
+    if lib().orc_linpred(_p(X), code, ldx, _p(scale), N, K, _p(beta), _p(u)):
+        raise ValueError("oracle rejected its arguments")
+    return u
+
+
+def logpost_grad_multi(X, y, betas, prec, means=None, dtype=None, scale=None, family="logistic"):
     """Several betas (b x K) on one data set; returns a b x (1 + K) array."""
     code, ldx, X = _xinfo(X, dtype)
     N, K = X.shape
@@ -117,13 +132,15 @@ def logpost_grad_multi(X, y, betas, prec, means=None, dtype=None, scale=None):
     scale = None if scale is None else np.ascontiguousarray(scale, np.float32)
     out = np.empty((betas.shape[0], 1 + K))
     rc = lib().orc_logpost_grad_multi(_p(X), code, ldx, _p(scale), _p(y), N, K, _p(betas),
-                                      betas.shape[0], float(prec), _p(means), _p(out))
+                                      betas.shape[0], float(prec), _p(means), FAMILIES[family],
+                                      _p(out))
     if rc:
         raise ValueError("oracle rejected its arguments")
     return out
 
 
-def logpost_grad_groups(X, y, offsets, betas, prec, mean=None, dtype=None, scale=None):
+def logpost_grad_groups(X, y, offsets, betas, prec, mean=None, dtype=None, scale=None,
+                        family="logistic"):
     """Hierarchical groups stacked row-wise; returns a G x (1 + K) array."""
     code, ldx, X = _xinfo(X, dtype)
     K = X.shape[1]
@@ -138,7 +155,8 @@ def logpost_grad_groups(X, y, offsets, betas, prec, mean=None, dtype=None, scale
     scale = None if scale is None else np.ascontiguousarray(scale, np.float32)
     out = np.empty((G, 1 + K))
     rc = lib().orc_logpost_grad_groups(_p(X), code, ldx, _p(scale), _p(y), _p(offsets), G, K,
-                                       _p(betas), float(prec), _p(mean), per_group, _p(out))
+                                       _p(betas), float(prec), _p(mean), per_group,
+                                       FAMILIES[family], _p(out))
     if rc:
         raise ValueError("oracle rejected its arguments")
     return out

@@ -17,7 +17,12 @@
  *           is -prec/2 |beta - m|^2 with gradient -prec (beta - m).
  *   f     = L - prec/2 |beta - m|^2,   g = g_L - prec (beta - m).
  *
- * The response y_n must be 0 or 1.  softplus and sigmoid are evaluated in the
+ * Poisson regression (log link; the paper notes that only the per-row map
+ * changes for other GLMs, Sec. 3.4) replaces the per-row terms by
+ *   t_n = y_n u_n - exp(u_n),  r_n = y_n - exp(u_n)   (y_n a count 0..255),
+ * leaving out the constant -log(y_n!).
+ *
+ * For the logistic model the response y_n must be 0 or 1.  softplus and sigmoid are evaluated in the
  * overflow-free forms softplus(u) = max(u,0) + log1p(exp(-|u|)) and
  * sigmoid(u) = 1/(1+exp(-u)) (u >= 0) or exp(u)/(1+exp(u)) (u < 0); in exact
  * arithmetic these equal log(1+exp(u)) and 1/(1+exp(-u)).
@@ -43,6 +48,7 @@
 #include <string.h>
 
 enum { ORC_F64 = 0, ORC_F32 = 1, ORC_BF16 = 2, ORC_FP8 = 3 };
+enum { ORC_LOGISTIC = 0, ORC_POISSON = 1 };
 
 /* ---------------------------------------------------------------- decoding */
 
@@ -112,8 +118,9 @@ double orc_sigmoid(double u) {
  */
 int orc_logpost_grad(const void* X, int dtype, int64_t ldx, const float* scale,
                      const uint8_t* y, int64_t N, int K, const double* beta,
-                     double prec, const double* mean, double* out) {
+                     double prec, const double* mean, int family, double* out) {
     if (K < 1 || N < 0 || ldx < K || !beta || !out) return -1;
+    if (family != ORC_LOGISTIC && family != ORC_POISSON) return -1;
     if (dtype < ORC_F64 || dtype > ORC_FP8) return -1;
     if (N > 0 && (!X || !y)) return -1;
     if (dtype == ORC_FP8 && N > 0 && !scale) return -1;
@@ -124,15 +131,24 @@ int orc_logpost_grad(const void* X, int dtype, int64_t ldx, const float* scale,
     if (!g || !x) { free(g); free(x); return -1; }
 
     for (int64_t n = 0; n < N; ++n) {
-        if (y[n] > 1) { free(g); free(x); return -1; }
+        if (family == ORC_LOGISTIC && y[n] > 1) { free(g); free(x); return -1; }
         double yn = (double)y[n];
         double u = 0.0;
         for (int k = 0; k < K; ++k) {
             x[k] = elem(X, dtype, n * ldx + k, scale, k);
             u += x[k] * beta[k];
         }
-        nsum_add(&f, yn * u - orc_softplus(u));
-        double r = yn - orc_sigmoid(u);
+        double t, r;
+        if (family == ORC_LOGISTIC) {
+            t = yn * u - orc_softplus(u);
+            r = yn - orc_sigmoid(u);
+        } else {
+            /* Poisson with log link: log p(y | u) = y u - exp(u) - log(y!),
+             * the last term constant in beta and left out */
+            t = yn * u - exp(u);
+            r = yn - exp(u);
+        }
+        nsum_add(&f, t);
         for (int k = 0; k < K; ++k) nsum_add(&g[k], r * x[k]);
     }
 
@@ -148,14 +164,30 @@ int orc_logpost_grad(const void* X, int dtype, int64_t ldx, const float* scale,
     return 0;
 }
 
+/* Linear predictor u_n = sum_k x_nk beta_k (FP64, k order), the quantity the
+ * differential update (Sec. 3.4.4) keeps resident between steps. */
+int orc_linpred(const void* X, int dtype, int64_t ldx, const float* scale, int64_t N, int K,
+                const double* beta, double* u) {
+    if (K < 1 || N < 0 || ldx < K || !beta) return -1;
+    if (dtype < ORC_F64 || dtype > ORC_FP8) return -1;
+    if (N > 0 && (!X || !u)) return -1;
+    if (dtype == ORC_FP8 && N > 0 && !scale) return -1;
+    for (int64_t n = 0; n < N; ++n) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) acc += elem(X, dtype, n * ldx + k, scale, k) * beta[k];
+        u[n] = acc;
+    }
+    return 0;
+}
+
 /* Several evaluation points on one data set: betas and out are b x K and
  * b x (1 + K), row-major; means is b x K or NULL. */
 int orc_logpost_grad_multi(const void* X, int dtype, int64_t ldx, const float* scale,
                            const uint8_t* y, int64_t N, int K, const double* betas,
-                           int b, double prec, const double* means, double* out) {
+                           int b, double prec, const double* means, int family, double* out) {
     for (int i = 0; i < b; ++i) {
         int rc = orc_logpost_grad(X, dtype, ldx, scale, y, N, K, betas + (int64_t)i * K,
-                                  prec, means ? means + (int64_t)i * K : NULL,
+                                  prec, means ? means + (int64_t)i * K : NULL, family,
                                   out + (int64_t)i * (1 + K));
         if (rc) return rc;
     }
@@ -168,7 +200,7 @@ int orc_logpost_grad_multi(const void* X, int dtype, int64_t ldx, const float* s
 int orc_logpost_grad_groups(const void* X, int dtype, int64_t ldx, const float* scale,
                             const uint8_t* y, const int64_t* offsets, int G, int K,
                             const double* betas, double prec, const double* mean,
-                            int mean_per_group, double* out) {
+                            int mean_per_group, int family, double* out) {
     size_t es = dtype == ORC_F64 ? 8 : dtype == ORC_F32 ? 4 : dtype == ORC_BF16 ? 2 : 1;
     for (int g = 0; g < G; ++g) {
         int64_t a = offsets[g], b = offsets[g + 1];
@@ -176,7 +208,7 @@ int orc_logpost_grad_groups(const void* X, int dtype, int64_t ldx, const float* 
         const char* Xg = (const char*)X + (size_t)(a * ldx) * es;
         const double* mg = mean ? (mean_per_group ? mean + (int64_t)g * K : mean) : NULL;
         int rc = orc_logpost_grad(Xg, dtype, ldx, scale, y + a, b - a, K,
-                                  betas + (int64_t)g * K, prec, mg,
+                                  betas + (int64_t)g * K, prec, mg, family,
                                   out + (int64_t)g * (1 + K));
         if (rc) return rc;
     }

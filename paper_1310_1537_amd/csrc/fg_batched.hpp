@@ -42,6 +42,7 @@ struct BatchedParams {
     const int32_t* group_blocks;       // per group: number of distinct blocks holding its tiles
     double* partials;            // ntiles x (1 + K)
     unsigned* counters;          // G tickets, zero between launches
+    int family;                  // response family (0 logistic, 1 Poisson)
 };
 
 template <int DT, int LPR, int CPL, int R, int WPB>
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
     const int K1 = K + 1;
 
     WT wt;
-    wt.init(threadIdx.x & 63, K, p.ldx);
+    wt.init(threadIdx.x & 63, K, p.ldx, p.family);
     __shared__ typename WT::rtype rbuf[WPB][WT::RBUF];
 
     // The wave's items are streamed as one sequence of batches, so the next

@@ -76,6 +76,7 @@ struct FgParams {
     int nblocks;
     int group;                // blocks per merge group
     int interleave;           // 1: wave w takes batches w, w+W, ...; 0: one contiguous range
+    int family;               // response family (0 logistic, 1 Poisson)
 };
 
 // ------------------------------------------------------------ decoding
@@ -224,8 +225,18 @@ __device__ __forceinline__ double cross_segment_sum(double v) {
 
 // ------------------------------------------------------------ TR map
 
-// t = y u - softplus(u), r = y - sigmoid(u), overflow-free, in FP64.
-__device__ __forceinline__ void tr_map(double u, double yv, double& t, double& r) {
+// Per-row terms in FP64 for the response family fam (wave-uniform):
+//   logistic (0): t = y u - softplus(u), r = y - sigmoid(u), overflow-free;
+//   Poisson  (1): t = y u - exp(u),      r = y - exp(u)  (y a count 0..255).
+__device__ __forceinline__ void tr_map(double u, unsigned yb, int fam, double& t, double& r) {
+    if (fam == 1) {
+        const double yv = (double)(yb & 0xFFu);
+        const double mu = exp(u);
+        t = yv * u - mu;
+        r = yv - mu;
+        return;
+    }
+    const double yv = (double)(yb & 1u);
     const double e = exp(-fabs(u));
     const double sp = fmax(u, 0.0) + log1p(e);
     const double inv = 1.0 / (1.0 + e);
@@ -358,6 +369,7 @@ struct WaveTile {
     };
 
     int lane, seg, cl, NC, KC;
+    int fam;                 // response family (wave-uniform)
     bool ragged;             // K * ES is not a whole number of chunks (wave-uniform)
     u32x4 xmask[CPL];        // bytes of chunk i that are columns < K (ragged K only)
     uint32_t ldb;            // row stride in bytes
@@ -369,8 +381,9 @@ struct WaveTile {
     double g64[NB][CPL][VE];                  // this lane's gradient columns
     double facc[NB];
 
-    __device__ __forceinline__ void init(int lane_, int K, int64_t ldx) {
+    __device__ __forceinline__ void init(int lane_, int K, int64_t ldx, int family) {
         lane = lane_;
+        fam = family;
         seg = lane / LPR;
         cl = lane % LPR;
         // A row of K columns spans NC chunks; when K * ES is not a multiple
@@ -524,7 +537,7 @@ struct WaveTile {
 #pragma unroll
             for (int o = 0; o < OWN; ++o) {
                 double tt, rr;
-                tr_map(uo[o], (double)(t.yb[o] & 1u), tt, rr);
+                tr_map(uo[o], t.yb[o], fam, tt, rr);
                 const bool ok = yoff[o] < nvalid;
                 if (ok && unique) facc[b] += tt;
                 if (unique) {
@@ -622,7 +635,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     WT wt;
     // wave-uniform: keeps the batch bookkeeping and buffer bases in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    wt.init(threadIdx.x & 63, p.K, p.ldx);
+    wt.init(threadIdx.x & 63, p.K, p.ldx, p.family);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (b < p.nb) {

@@ -246,6 +246,7 @@ glm_status launch_batched(glm_groupset* gs, const double* betas, const glm_prior
     p.group_blocks = gs->d_group_blocks;
     p.partials = gs->d_partials;
     p.counters = gs->d_counters;
+    p.family = gs->d.family;
     void* args[] = {&p};
     GLM_HIP_CHECK(hipLaunchKernel(gs->fn, dim3(gs->nblocks), dim3(gs->wpb * 64), args, 0, stream));
     return GLM_OK;

@@ -30,6 +30,8 @@ glm_status validate_desc(const glm_dataset_desc& dd) {
     if (d->N > 0 && (!d->X || !d->y)) GLM_FAIL(GLM_EINVAL, "data set: X or y is NULL");
     if (d->X && ((uintptr_t)d->X % es))
         GLM_FAIL(GLM_EINVAL, "data set: X not aligned to its %d-byte element", es);
+    if (d->family != GLM_LOGISTIC && d->family != GLM_POISSON)
+        GLM_FAIL(GLM_EINVAL, "data set: unknown response family %d", d->family);
     if (d->dtype == GLM_FP8_E4M3 && !d->col_scale)
         GLM_FAIL(GLM_EINVAL, "data set: FP8 data needs col_scale");
     if (d->dtype != GLM_FP8_E4M3 && d->col_scale)

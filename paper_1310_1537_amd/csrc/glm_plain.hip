@@ -132,6 +132,7 @@ glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* f
     p.nblocks = pl.nblocks;
     p.group = pl.group;
     p.interleave = pl.interleave;
+    p.family = d.family;
     (void)NB;
     void* args[] = {&p};
     GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0, stream));

@@ -67,6 +67,12 @@ struct Dataset {
     Plan plan;
 };
 
+// Column-major copy of a data set (differential update).
+struct ColSet {
+    glm_colset_desc d;
+    std::vector<float> scale_host;   // FP8 column scales, read once at registration
+};
+
 // Device scratch of one stream: block partials, group partials, tickets.
 struct Scratch {
     void* base = nullptr;
@@ -90,6 +96,7 @@ struct glm_ctx {
     std::mutex mu;
     int64_t next_id = 1;
     std::unordered_map<int64_t, glmrt::Dataset> datasets;
+    std::unordered_map<int64_t, glmrt::ColSet> colsets;
     std::map<void*, glmrt::Scratch> scratch;   // keyed by stream
     hipStream_t own_stream = nullptr;
     // host-call staging (pinned) and device buffers

@@ -24,6 +24,7 @@ GLM_OK, GLM_PENDING = 0, 1
 GLM_EINVAL, GLM_EDTYPE, GLM_EHIP, GLM_ENOTFOUND = -1, -2, -3, -4
 GLM_EBUDGET, GLM_ECANCELLED, GLM_EAGAIN, GLM_ENOMEM = -5, -6, -7, -8
 GLM_F64, GLM_F32, GLM_BF16, GLM_FP8_E4M3 = 0, 1, 2, 3
+GLM_LOGISTIC, GLM_POISSON = 0, 1
 GLM_K_MAX = 4096
 
 STATUS_NAMES = {0: "GLM_OK", 1: "GLM_PENDING", -1: "GLM_EINVAL", -2: "GLM_EDTYPE",
@@ -40,7 +41,7 @@ class GlmError(RuntimeError):
 class glm_dataset_desc(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("dtype", ctypes.c_int32),
                 ("col_scale", ctypes.c_void_p), ("y", ctypes.c_void_p), ("N", ctypes.c_int64),
-                ("K", ctypes.c_int32)]
+                ("K", ctypes.c_int32), ("family", ctypes.c_int32)]
 
 
 class glm_groupset_info_t(ctypes.Structure):
@@ -64,6 +65,12 @@ class glm_server_stats_t(ctypes.Structure):
                 ("queue_depth", ctypes.c_int32), ("pass_width_hist", ctypes.c_uint64 * 9),
                 ("latency_p50_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
                 ("latency_mean_us", ctypes.c_double)]
+
+
+class glm_colset_desc(ctypes.Structure):
+    _fields_ = [("Xt", ctypes.c_void_p), ("ldt", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("col_scale", ctypes.c_void_p), ("y", ctypes.c_void_p), ("N", ctypes.c_int64),
+                ("K", ctypes.c_int32), ("family", ctypes.c_int32)]
 
 
 class glm_prior(ctypes.Structure):
@@ -102,6 +109,12 @@ _SIGS = {
     "glm_server_reset_stats": [_P],
     "glm_server_shutdown": [_P],
     "glm_server_destroy": [_P],
+    "glm_transpose": [_P, ctypes.POINTER(glm_dataset_desc), _P, _I64, _P],
+    "glm_colset_register": [_P, ctypes.POINTER(glm_colset_desc), ctypes.POINTER(_I64)],
+    "glm_colset_unregister": [_P, _I64],
+    "glm_linpred": [_P, _I64, _P, _P, _P],
+    "glm_diff_logpost": [_P, _I64, _P, _P, _I32, _P, _I32, ctypes.POINTER(glm_prior), _P, _P],
+    "glm_diff_commit": [_P, _I64, _P, _P, _I32, _P, _P],
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_probe_read_bandwidth": [_P, _P, _I64, _I32, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
@@ -172,7 +185,8 @@ def glm_destroy(ctx: int) -> None:
 
 # ---------------------------------------------------------------- data sets
 
-def make_desc(X, y, N=None, K=None, ldx=None, dtype=None, col_scale=None) -> glm_dataset_desc:
+def make_desc(X, y, N=None, K=None, ldx=None, dtype=None, col_scale=None,
+              family: int = 0) -> glm_dataset_desc:
     """Descriptor for a row-major X (2-D tensor, or address with explicit
     N/K/ldx/dtype) and its uint8 response y."""
     if isinstance(X, torch.Tensor):
@@ -185,7 +199,7 @@ def make_desc(X, y, N=None, K=None, ldx=None, dtype=None, col_scale=None) -> glm
             assert X.stride(1) == 1, "X must be row-major"
             ldx = X.stride(0) if ldx is None else ldx
         dtype = _dtype_code(X, dtype)
-    return glm_dataset_desc(_ptr(X), ldx, dtype, _ptr(col_scale), _ptr(y), N, K)
+    return glm_dataset_desc(_ptr(X), ldx, dtype, _ptr(col_scale), _ptr(y), N, K, family)
 
 
 def aligned_rows(X):
@@ -242,6 +256,51 @@ def glm_logpost_grad_host(ctx: int, ds: int, beta_host, prior: glm_prior, g_host
     return f.value
 
 
+# ---------------------------------------------------------------- differential update
+
+def glm_transpose(ctx: int, desc: glm_dataset_desc, Xt, ldt: int | None = None, stream=None) -> None:
+    """Column-major copy of desc's X into the device buffer Xt (K x ldt)."""
+    if ldt is None:
+        ldt = Xt.stride(0) if isinstance(Xt, torch.Tensor) else desc.N
+    _check(_lib.glm_transpose(ctx, ctypes.byref(desc), _ptr(Xt), int(ldt), _stream(stream)))
+
+
+def make_colset_desc(Xt, y, N=None, dtype=None, col_scale=None,
+                     family: int = 0) -> glm_colset_desc:
+    """Descriptor of a column-major copy: Xt a K x ldt device tensor whose
+    row k is column k of X (first N entries used)."""
+    assert Xt.dim() == 2 and Xt.stride(1) == 1
+    K = Xt.shape[0]
+    N = Xt.shape[1] if N is None else N
+    ldt = Xt.stride(0) if Xt.numel() else max(N, 1)
+    return glm_colset_desc(_ptr(Xt), ldt, _dtype_code(Xt, dtype), _ptr(col_scale), _ptr(y), N, K,
+                           family)
+
+
+def glm_colset_register(ctx: int, desc: glm_colset_desc) -> int:
+    out = ctypes.c_int64()
+    _check(_lib.glm_colset_register(ctx, ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def glm_colset_unregister(ctx: int, cs: int) -> None:
+    _check(_lib.glm_colset_unregister(ctx, cs))
+
+
+def glm_linpred(ctx: int, cs: int, beta, u, stream=None) -> None:
+    _check(_lib.glm_linpred(ctx, cs, _ptr(beta), _ptr(u), _stream(stream)))
+
+
+def glm_diff_logpost(ctx: int, cs: int, u, beta, k: int, deltas, nd: int, prior: glm_prior, f_out,
+                     stream=None) -> None:
+    _check(_lib.glm_diff_logpost(ctx, cs, _ptr(u), _ptr(beta), k, _ptr(deltas), nd,
+                                 ctypes.byref(prior), _ptr(f_out), _stream(stream)))
+
+
+def glm_diff_commit(ctx: int, cs: int, u, beta, k: int, delta, stream=None) -> None:
+    _check(_lib.glm_diff_commit(ctx, cs, _ptr(u), _ptr(beta), k, _ptr(delta), _stream(stream)))
+
+
 # ---------------------------------------------------------------- batched
 
 def glm_groupset_create(ctx: int, desc: glm_dataset_desc, offsets, tune: bool = True) -> int:
@@ -280,7 +339,7 @@ def glm_server_create(ctx: int, hbm_budget_bytes: int, max_beta_per_pass: int = 
     return out.value
 
 
-def make_host_desc(X, y, dtype=None, col_scale=None) -> glm_dataset_desc:
+def make_host_desc(X, y, dtype=None, col_scale=None, family: int = 0) -> glm_dataset_desc:
     """Descriptor with host pointers for numpy X (row-major) and y."""
     import numpy as np
     assert X.ndim == 2 and X.strides[1] == X.itemsize
@@ -289,7 +348,7 @@ def make_host_desc(X, y, dtype=None, col_scale=None) -> glm_dataset_desc:
                  np.dtype(np.uint16): GLM_BF16, np.dtype(np.uint8): GLM_FP8_E4M3}[X.dtype]
     return glm_dataset_desc(X.ctypes.data, X.strides[0] // X.itemsize, dtype,
                             None if col_scale is None else col_scale.ctypes.data,
-                            y.ctypes.data, X.shape[0], X.shape[1])
+                            y.ctypes.data, X.shape[0], X.shape[1], family)
 
 
 def glm_server_add_dataset(srv: int, desc: glm_dataset_desc, on_device: bool = False) -> int:

@@ -115,6 +115,32 @@ def logistic_labels(X: np.ndarray, beta_true: np.ndarray,
     return y
 
 
+def poisson_counts(X: np.ndarray, beta_true: np.ndarray, ss: np.random.SeedSequence,
+                   cap: int = 255) -> np.ndarray:
+    """y_n ~ Poisson(exp(x_n . beta_true)) truncated at cap (stored as bytes);
+    linear predictor in float64 on the stored values of X, drawn in row
+    chunks with their own child seeds."""
+    N = X.shape[0]
+    y = np.empty(N, np.uint8)
+    nchunks = max(1, -(-N // CHUNK_ROWS))
+    kids = ss.spawn(nchunks)
+    bt = np.asarray(beta_true, np.float64)
+
+    def fill(c: int) -> None:
+        a, b = c * CHUNK_ROWS, min(N, (c + 1) * CHUNK_ROWS)
+        if a >= b:
+            return
+        rate = np.exp(X[a:b].astype(np.float64) @ bt)
+        y[a:b] = np.minimum(_rng(kids[c]).poisson(rate), cap)
+
+    if nchunks == 1:
+        fill(0)
+    else:
+        with ThreadPoolExecutor(_n_threads()) as ex:
+            list(ex.map(fill, range(nchunks)))
+    return y
+
+
 def random_walk(start_mean: np.ndarray, n: int, ss: np.random.SeedSequence,
                 start_sd: float = 0.1, step_sd: float = 0.01) -> np.ndarray:
     """beta_0 ~ N(start_mean, start_sd^2 I), beta_{t+1} = beta_t + N(0, step_sd^2 I);
@@ -183,6 +209,22 @@ def plain_big(N: int = 4_000_000, K: int = 256, n_evals: int = 1000,
     return Plain(X, y, bt, betas, 1.0 / 100.0,
                  f"plain_big_n{N}_k{K}_{np.dtype(dtype).name}",
                  {"n_binary": nb})
+
+
+def plain_poisson(N: int = 4_000_000, K: int = 256, n_evals: int = 1000,
+                  dtype=np.float32) -> Plain:
+    """Poisson regression on the big plain shape: X as plain_big (last
+    round(0.1 K) columns Bernoulli(0.3)), beta_true ~ N(0, 1/(4K)) so that
+    the rates exp(x . beta_true) stay moderate, y ~ Poisson(rate) as bytes,
+    prior sd 10, the same random-walk trajectory recipe."""
+    s = streams(seed_seq(5))
+    nb = int(round(0.1 * K))
+    X = design_matrix(N, K, s["X"], dtype, n_binary=nb, p_binary=0.3)
+    bt = 0.5 * true_coefficients(K, s["beta_true"])
+    y = poisson_counts(X, bt, s["y"])
+    betas = random_walk(bt, n_evals, s["trajectory"])
+    return Plain(X, y, bt, betas, 1.0 / 100.0,
+                 f"plain_poisson_n{N}_k{K}_{np.dtype(dtype).name}", {"n_binary": nb})
 
 
 def precision_big(N: int = 8_000_000, K: int = 512, n_evals: int = 1000) -> Plain:

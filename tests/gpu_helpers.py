@@ -14,7 +14,8 @@ most 16 rows are FP32 (relative error <= 18 * 2^-24), then FP64.  Hence
 
 plus FP64 rounding, which the bounds cover with a 1e-12 relative margin.
 For FP64 storage gamma = (K + 2) 2^-53 and the accumulation terms use 2^-53
-per row of the longest per-lane chain.
+per row of the longest per-lane chain.  For the Poisson model r = y - exp(u),
+so |dr| <= exp(u) |du| + 2^-24 |r| takes the place of the 1/4 above.
 """
 from __future__ import annotations
 
@@ -42,12 +43,14 @@ class Ctx:
 
 
 def eval_gpu(ctx: int, X: torch.Tensor, y: torch.Tensor, beta: np.ndarray, prec: float,
-             mean: np.ndarray | None = None, dtype=None, scale=None, stream=None, ds=None):
+             mean: np.ndarray | None = None, dtype=None, scale=None, stream=None, ds=None,
+             family: int = 0):
     """f, g on the GPU through glm_logpost_grad (registers a data set unless
     ds is given)."""
     own = ds is None
     if own:
-        ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y, dtype=dtype, col_scale=scale))
+        ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y, dtype=dtype, col_scale=scale,
+                                                         family=family))
     K = X.shape[1]
     b = to_dev(np.asarray(beta, np.float64))
     m = None if mean is None else to_dev(np.asarray(mean, np.float64))
@@ -61,19 +64,27 @@ def eval_gpu(ctx: int, X: torch.Tensor, y: torch.Tensor, beta: np.ndarray, prec:
 
 
 def bounds(Xd: np.ndarray, y: np.ndarray, beta: np.ndarray, f_ref: float, g_ref: np.ndarray,
-           storage: str = "f32"):
-    """(bound on |df|, per-component bound on |dg|) for the given decoded X."""
+           storage: str = "f32", family: str = "logistic"):
+    """(bound on |df|, per-component bound on |dg|) for the given decoded X.
+    The residual's sensitivity |dr/du| is 1/4 for the logistic model and
+    exp(u) for the Poisson one."""
     K = Xd.shape[1]
     eps = 2.0 ** -53 if storage == "f64" else 2.0 ** -24
     gamma = (K + 2) * eps
     u = Xd @ beta
-    r = y - 0.5 * (1.0 + np.tanh(0.5 * u))
+    yv = y.astype(np.float64)
+    if family == "poisson":
+        mu = np.exp(u)
+        r, slope, tmag = yv - mu, mu, np.abs(yv * u) + mu
+    else:
+        r, slope, tmag = yv - 0.5 * (1.0 + np.tanh(0.5 * u)), 0.25, np.abs(u) + 1
     A = np.abs(Xd) @ np.abs(beta)
     acc = (np.abs(r) * 20 * eps) if storage != "f64" else (np.abs(r) * (len(y) + 20) * eps)
-    bf = gamma * np.sum(np.abs(r) * A) + 1e-12 * abs(f_ref) + 1e-12 * np.sum(np.abs(u) + 1)
+    bf = gamma * np.sum(np.abs(r) * A) + 1e-12 * abs(f_ref) + 1e-12 * np.sum(tmag)
     if storage == "f64":
-        bf += (len(y) + 64) * eps * np.sum(np.abs(u) + 1)
-    bg = np.abs(Xd).T @ (gamma * A / 4 + acc) + 1e-12 * (np.abs(Xd).T @ np.abs(r)) + 1e-12 * np.abs(g_ref)
+        bf += (len(y) + 64) * eps * np.sum(tmag)
+    bg = (np.abs(Xd).T @ (gamma * A * slope + acc) + 1e-12 * (np.abs(Xd).T @ np.abs(r))
+          + 1e-12 * np.abs(g_ref))
     return bf, bg
 
 
@@ -84,7 +95,7 @@ def check_against_oracle(got_f, got_g, Xd, y, beta, prec, mean=None, storage="f3
     oracle_kw = oracle_kw or {}
     Xo = Xd if X_for_oracle is None else X_for_oracle
     f, g = oracle.logpost_grad(Xo, y, beta, prec, mean, **oracle_kw)
-    bf, bg = bounds(Xd, y, beta, f, g, storage)
+    bf, bg = bounds(Xd, y, beta, f, g, storage, oracle_kw.get("family", "logistic"))
     ef = abs(got_f - f)
     eg = np.abs(got_g - g)
     assert np.isfinite(got_f) and np.all(np.isfinite(got_g))

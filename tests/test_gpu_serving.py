@@ -244,7 +244,8 @@ def test_multi_ragged_k(ctx, K):
     buf = np.full((X.shape[0], ld), np.nan, np.float32)
     buf[:, :K] = X
     Xd = torch.from_numpy(buf).to(DEV)[:, :K]
-    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, to_dev(y)))
+    yd = to_dev(y)          # the data set borrows X and y: keep both alive
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
     B = _betas(bt, 6, 81)
     out = torch.empty((6, K + 1), dtype=torch.float64, device=DEV)
     glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), 6, glm.make_prior(0.01), out)

@@ -383,3 +383,147 @@ def test_golden_record_of_small_workload():
         assert np.array_equal(np.array(p["beta"]), beta)
         f, g = oracle.logpost_grad(w.X, w.y, beta, w.prec)
         assert f == p["f"] and np.array_equal(g, np.array(p["g"]))
+
+
+# ------------------------------------------------------------ linear predictor
+
+def test_linpred_exact_on_dyadic_inputs():
+    """Small integers times dyadic coefficients: every product and partial sum
+    is exact in FP64, so u must equal the rational result exactly."""
+    from fractions import Fraction
+    g = np.random.default_rng(21)
+    X = g.integers(-50, 51, (300, 9)).astype(np.float64)
+    beta = g.integers(-1000, 1001, 9) / 256.0
+    u = oracle.linpred(X, beta)
+    for n in range(300):
+        want = sum(Fraction(int(X[n, k])) * Fraction(beta[k]) for k in range(9))
+        assert Fraction(u[n]) == want
+
+
+def test_linpred_is_what_the_log_posterior_uses():
+    """sum_n u_n = f(y=1) - f(y=0) (response linearity of the likelihood), and
+    for stored BF16 / FP8 codes u equals u of the decoded values."""
+    X, _, beta = _data(1500, 12, 22)
+    N = X.shape[0]
+    u = oracle.linpred(X, beta)
+    f1, _ = oracle.logpost_grad(X, np.ones(N, np.uint8), beta, 0.0)
+    f0, _ = oracle.logpost_grad(X, np.zeros(N, np.uint8), beta, 0.0)
+    assert abs(math.fsum(u) - (f1 - f0)) < 1e-13 * (math.fsum(np.abs(u)) + N)
+    X32 = X.astype(np.float32)
+    Qb = oracle.quantize_bf16(X32)
+    np.testing.assert_array_equal(oracle.linpred(Qb, beta, dtype="bf16"),
+                                  oracle.linpred(oracle.decode_bf16(Qb), beta))
+    Q8, s8 = oracle.quantize_fp8(X32)
+    np.testing.assert_array_equal(oracle.linpred(Q8, beta, dtype="fp8", scale=s8),
+                                  oracle.linpred(oracle.decode_fp8(Q8, s8), beta))
+
+
+# --------------------------------------------------------- Poisson family
+
+def _pdata(N, K, seed):
+    g = np.random.default_rng(seed)
+    X = g.standard_normal((N, K))
+    beta = 0.5 * g.standard_normal(K) / math.sqrt(K)
+    y = np.minimum(g.poisson(np.exp(X @ beta)), 255).astype(np.uint8)
+    return X, y, beta
+
+
+def test_poisson_closed_forms_at_zero():
+    """beta = 0: every row has u = 0, t = -exp(0) = -1 and r = y - 1, so
+    f(0) = -N and g(0) = X^t (y - 1) exactly."""
+    X, y, _ = _pdata(3000, 7, 30)
+    f, g = oracle.logpost_grad(X, y, np.zeros(7), 0.4, family="poisson")
+    assert f == -3000.0
+    want = [math.fsum(X[:, k] * (y.astype(np.float64) - 1.0)) for k in range(7)]
+    np.testing.assert_allclose(g, want, rtol=0, atol=1e-12 * 3000)
+
+
+def test_poisson_response_linearity():
+    """f(y) - f(y') = sum_n (y_n - y'_n) u_n and g(y) - g(y') = X^t (y - y'),
+    whatever beta is: the counts enter linearly."""
+    X, y, beta = _pdata(2000, 6, 31)
+    y2 = np.random.default_rng(32).integers(0, 40, 2000).astype(np.uint8)
+    f1, g1 = oracle.logpost_grad(X, y, beta, 0.1, family="poisson")
+    f2, g2 = oracle.logpost_grad(X, y2, beta, 0.1, family="poisson")
+    dy = y.astype(np.float64) - y2
+    u = oracle.linpred(X, beta)
+    assert abs((f1 - f2) - math.fsum(dy * u)) < 1e-12 * (math.fsum(np.abs(dy * u)) + 1)
+    want = [math.fsum(X[:, k] * dy) for k in range(6)]
+    np.testing.assert_allclose(g1 - g2, want, rtol=0, atol=1e-10 * 2000)
+
+
+def test_poisson_matches_torch_nll_and_autograd():
+    """torch's PoissonNLLLoss on log-rates (without the Stirling term) is
+    sum exp(u) - y u, minus the log-likelihood up to the left-out constant."""
+    torch = pytest.importorskip("torch")
+    X, y, beta = _pdata(5000, 10, 33)
+    m = np.full(10, 0.03)
+    lam = 0.5
+    f, g = oracle.logpost_grad(X, y, beta, lam, m, family="poisson")
+    b = torch.tensor(beta, requires_grad=True)
+    u = torch.from_numpy(X) @ b
+    d = b - torch.from_numpy(m)
+    loss = torch.nn.PoissonNLLLoss(log_input=True, full=False, reduction="sum")(
+        u, torch.from_numpy(y.astype(np.float64)))
+    ft = -loss - 0.5 * lam * (d * d).sum()
+    ft.backward()
+    assert _rel(f, ft.item()) < 1e-12
+    np.testing.assert_allclose(g, b.grad.numpy(), rtol=1e-10, atol=1e-9)
+
+
+def test_poisson_gradient_vanishes_at_sklearn_map_estimate():
+    """scikit-learn's PoissonRegressor (no intercept) minimises
+    mean half-deviance + alpha/2 |w|^2, whose stationary point is that of the
+    Poisson log-posterior with prior precision N alpha."""
+    sk = pytest.importorskip("sklearn.linear_model")
+    X, y, _ = _pdata(400, 5, 34)
+    alpha = 0.05
+    reg = sk.PoissonRegressor(alpha=alpha, fit_intercept=False, tol=1e-12, max_iter=10_000)
+    reg.fit(X, y)
+    w = reg.coef_.ravel()
+    lam = 400 * alpha
+    _, g = oracle.logpost_grad(X, y, w, lam, family="poisson")
+    assert np.linalg.norm(g) < 1e-5 * lam * np.linalg.norm(w)
+    _, gwrong = oracle.logpost_grad(X, y, w, 2 * lam, family="poisson")
+    assert np.linalg.norm(gwrong) > 0.5 * lam * np.linalg.norm(w)
+
+
+def test_poisson_complex_step_and_40_digit_brute_force():
+    X, y, beta = _pdata(30, 5, 35)
+    m = np.linspace(-0.1, 0.1, 5)
+    lam = 0.7
+    f, g = oracle.logpost_grad(X, y, beta, lam, m, family="poisson")
+    h = 1e-30
+    for k in range(5):
+        bc = beta.astype(np.complex128)
+        bc[k] += 1j * h
+        uc = X @ bc
+        dd = bc - m
+        fc = np.sum(y * uc - np.exp(uc)) - 0.5 * lam * np.sum(dd * dd)
+        assert abs(g[k] - fc.imag / h) < 1e-12 * max(1.0, abs(g[k]))
+    getcontext().prec = 40
+    D = Decimal
+    fs = D(0)
+    gs = [D(0)] * 5
+    for n in range(30):
+        u = sum(D(float(X[n, k])) * D(float(beta[k])) for k in range(5))
+        mu = u.exp()
+        fs += D(int(y[n])) * u - mu
+        gs = [gs[k] + (D(int(y[n])) - mu) * D(float(X[n, k])) for k in range(5)]
+    dd = [D(float(beta[k])) - D(float(m[k])) for k in range(5)]
+    fs -= D(lam) / 2 * sum(d * d for d in dd)
+    gs = [gs[k] - D(lam) * dd[k] for k in range(5)]
+    assert _rel(f, float(fs)) < 1e-15
+    for k in range(5):
+        assert abs(g[k] - float(gs[k])) < 1e-14 * max(1.0, abs(float(gs[k])))
+
+
+def test_poisson_rejects_nothing_the_logistic_model_rejects_for_counts():
+    """Counts above 1 are invalid for the logistic model and valid for the
+    Poisson one."""
+    X, y, beta = _pdata(50, 3, 36)
+    y[0] = 7
+    with pytest.raises(ValueError):
+        oracle.logpost_grad(X, y, beta, 0.1)
+    f, _ = oracle.logpost_grad(X, y, beta, 0.1, family="poisson")
+    assert np.isfinite(f)

@@ -71,3 +71,15 @@ def test_mh_proposal_scale():
     assert abs(sd - 2.38 / math.sqrt(512) / math.sqrt(1.6e6)) < 1e-15
     assert abs(inc.std() / sd - 1) < 0.01
     assert (logu < 0).all()
+
+
+def test_poisson_counts_deterministic_and_calibrated():
+    """Same seeds give the same counts whatever the worker count; the counts
+    average the rates exp(x . beta) (a calibration check, 5 sigma)."""
+    w1 = synth.plain_poisson(N=200_000, K=16, n_evals=2)
+    w2 = synth.plain_poisson(N=200_000, K=16, n_evals=2)
+    assert np.array_equal(w1.y, w2.y) and np.array_equal(w1.X, w2.X)
+    rate = np.exp(w1.X.astype(np.float64) @ w1.beta_true)
+    se = math.sqrt(rate.sum())
+    assert abs(w1.y.sum() - rate.sum()) < 5 * se
+    assert w1.y.max() < 255
