@@ -40,6 +40,8 @@
 
 #include <type_traits>
 
+#include "tr_math.hpp"
+
 namespace glmk {
 
 enum : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_FP8 = 3 };
@@ -231,14 +233,14 @@ __device__ __forceinline__ double cross_segment_sum(double v) {
 __device__ __forceinline__ void tr_map(double u, unsigned yb, int fam, double& t, double& r) {
     if (fam == 1) {
         const double yv = (double)(yb & 0xFFu);
-        const double mu = exp(u);
+        const double mu = exp_f64(u);
         t = yv * u - mu;
         r = yv - mu;
         return;
     }
     const double yv = (double)(yb & 1u);
-    const double e = exp(-fabs(u));
-    const double sp = fmax(u, 0.0) + log1p(e);
+    const double e = exp_f64(-fabs(u));
+    const double sp = fmax(u, 0.0) + log1p_unit(e);
     const double inv = 1.0 / (1.0 + e);
     const double sig = u >= 0.0 ? inv : e * inv;
     t = yv * u - sp;

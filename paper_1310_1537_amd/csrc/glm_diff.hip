@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "runtime.hpp"
+#include "tr_math.hpp"
 
 namespace glmrt {
 namespace {
@@ -63,8 +64,8 @@ template <> struct Elem<GLM_FP8_E4M3> {
 // t(v) = y v - b(v) with b the log-partition of the response family:
 // softplus (logistic) or exp (Poisson, y a count).
 __device__ __forceinline__ double row_term(double v, unsigned yb, int fam) {
-    if (fam == GLM_POISSON) return (double)(yb & 0xFFu) * v - exp(v);
-    return (double)(yb & 1u) * v - (fmax(v, 0.0) + log1p(exp(-fabs(v))));
+    if (fam == GLM_POISSON) return (double)(yb & 0xFFu) * v - glmk::exp_f64(v);
+    return (double)(yb & 1u) * v - (fmax(v, 0.0) + glmk::log1p_unit(glmk::exp_f64(-fabs(v))));
 }
 
 // ---------------------------------------------------------------- transpose
@@ -132,37 +133,111 @@ struct DiffParams {
     double* partials;         // gridDim.x x nd
     unsigned* ticket;         // zero between launches
     int family;               // response family
+    int vec;                  // rows in aligned groups of four (see k_diff_eval)
 };
 
+// Four consecutive entries of a column as doubles, from one aligned vector
+// load (16 bytes for FP32, 8 for BF16, 4 for FP8, two 16-byte loads for FP64).
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+typedef unsigned uv2 __attribute__((ext_vector_type(2)));
+
 template <int DT>
-__global__ __launch_bounds__(kThreads) void k_diff_eval(DiffParams p) {
+__device__ __forceinline__ void load4(const void* col, int64_t n0, float s, double (&x)[4]) {
+    if constexpr (DT == GLM_F64) {
+        const dv2* p = reinterpret_cast<const dv2*>(static_cast<const double*>(col) + n0);
+        const dv2 a = __builtin_nontemporal_load(p), b = __builtin_nontemporal_load(p + 1);
+        x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+    } else if constexpr (DT == GLM_F32) {
+        const fv4 v = __builtin_nontemporal_load(
+            reinterpret_cast<const fv4*>(static_cast<const float*>(col) + n0));
+        x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else if constexpr (DT == GLM_BF16) {
+        const uv2 v = __builtin_nontemporal_load(
+            reinterpret_cast<const uv2*>(static_cast<const unsigned short*>(col) + n0));
+        x[0] = (double)__uint_as_float(v.x << 16);
+        x[1] = (double)__uint_as_float(v.x & 0xFFFF0000u);
+        x[2] = (double)__uint_as_float(v.y << 16);
+        x[3] = (double)__uint_as_float(v.y & 0xFFFF0000u);
+    } else {
+        const unsigned v = __builtin_nontemporal_load(
+            reinterpret_cast<const unsigned*>(static_cast<const unsigned char*>(col) + n0));
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)v, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)v, true);
+        x[0] = (double)lo[0] * (double)s; x[1] = (double)lo[1] * (double)s;
+        x[2] = (double)hi[0] * (double)s; x[3] = (double)hi[1] * (double)s;
+    }
+}
+
+// One block per compute unit (NT lanes): every block makes one agent-scope
+// release fence before its ticket, and those fences (L2 write-back) are what
+// a grid of many small blocks would pay for.
+//
+// Rows are taken in groups of four (one vector load of the column, two of
+// u, one of y), two groups per loop trip with all loads issued first; the
+// N mod 4 rows after the last group are taken one at a time.  The vector
+// loads need the column 4-element aligned, u 16-byte and y 4-byte aligned
+// (checked by the host, which otherwise launches with vec = false).
+template <int DT, int DMAX, int NT>
+__global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
+    static_assert(NT >= 256 && NT % 64 == 0, "the final merge uses 16 x 16 lanes");
     using E = Elem<DT>;
     const typename E::T* col = static_cast<const typename E::T*>(p.col);
     const int nd = p.nd;
-    double d[kDMax];
+    const int fam = p.family;
+    double d[DMAX];
 #pragma unroll
-    for (int j = 0; j < kDMax; ++j) d[j] = j < nd ? p.deltas[j] : 0.0;
-    double acc[kDMax];
+    for (int j = 0; j < DMAX; ++j) d[j] = j < nd ? p.deltas[j] : 0.0;
+    double acc[DMAX];
 #pragma unroll
-    for (int j = 0; j < kDMax; ++j) acc[j] = 0.0;
+    for (int j = 0; j < DMAX; ++j) acc[j] = 0.0;
 
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < p.N; n += stride) {
-        const double x = E::value(col[n], p.s);
-        const double un = p.u[n];
-        const unsigned yb = p.y[n];
+    auto add_row = [&](double x, double un, unsigned yb) {
 #pragma unroll
-        for (int j = 0; j < kDMax; ++j) {
+        for (int j = 0; j < DMAX; ++j) {
             if (j >= nd) break;
-            acc[j] += row_term(fma(d[j], x, un), yb, p.family);
+            acc[j] += row_term(fma(d[j], x, un), yb, fam);
         }
+    };
+
+    const int64_t gtid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    int64_t n_scalar = 0;   // first row of the one-at-a-time part
+    if (p.vec) {
+        const int64_t ng = p.N >> 2;
+        const dv2* u2 = reinterpret_cast<const dv2*>(p.u);
+        const unsigned* y4 = reinterpret_cast<const unsigned*>(p.y);
+        for (int64_t g = gtid; g < ng; g += 2 * stride) {
+            const int64_t g2 = g + stride;
+            const bool two = g2 < ng;
+            const int64_t gb = two ? g2 : g;   // a valid address either way
+            double xa[4], xb[4];
+            load4<DT>(p.col, 4 * g, p.s, xa);
+            load4<DT>(p.col, 4 * gb, p.s, xb);
+            const dv2 ua0 = u2[2 * g], ua1 = u2[2 * g + 1];
+            const dv2 ub0 = u2[2 * gb], ub1 = u2[2 * gb + 1];
+            const unsigned ya = y4[g], yb = y4[gb];
+            add_row(xa[0], ua0.x, ya & 0xFFu);
+            add_row(xa[1], ua0.y, (ya >> 8) & 0xFFu);
+            add_row(xa[2], ua1.x, (ya >> 16) & 0xFFu);
+            add_row(xa[3], ua1.y, ya >> 24);
+            if (two) {
+                add_row(xb[0], ub0.x, yb & 0xFFu);
+                add_row(xb[1], ub0.y, (yb >> 8) & 0xFFu);
+                add_row(xb[2], ub1.x, (yb >> 16) & 0xFFu);
+                add_row(xb[3], ub1.y, yb >> 24);
+            }
+        }
+        n_scalar = ng << 2;
     }
+    for (int64_t n = n_scalar + gtid; n < p.N; n += stride)
+        add_row(E::value(col[n], p.s), p.u[n], p.y[n]);
 
     // block partials: waves in order through LDS
-    __shared__ double s_w[kThreads / 64][kDMax];
+    __shared__ double s_w[NT / 64][DMAX];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < kDMax; ++j) {
+    for (int j = 0; j < DMAX; ++j) {
         if (j >= nd) break;
         double v = acc[j];
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -171,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_diff_eval(DiffParams p) {
     __syncthreads();
     if (threadIdx.x < nd) {
         double v = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) v += s_w[w][threadIdx.x];
+        for (int w = 0; w < NT / 64; ++w) v += s_w[w][threadIdx.x];
         p.partials[(int64_t)blockIdx.x * nd + threadIdx.x] = v;
     }
 
@@ -188,31 +263,34 @@ __global__ __launch_bounds__(kThreads) void k_diff_eval(DiffParams p) {
     __syncthreads();
     if (!s_last) return;
 
-    __shared__ double s_red[kThreads];
+    __shared__ double s_red[NT];
     double b = 0.0;   // sum over i != k of (beta_i - m_i)^2
-    for (int i = threadIdx.x; i < p.K; i += kThreads) {
+    for (int i = threadIdx.x; i < p.K; i += NT) {
         if (i == p.k) continue;
         const double di = p.beta[i] - (p.mean ? p.mean[i] : 0.0);
         b += di * di;
     }
     s_red[threadIdx.x] = b;
     __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
+    for (int w = NT / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
         __syncthreads();
     }
     // 16 fixed interleaved subsets of the blocks per step size, then the
     // subsets in order: a fixed summation order with the loads spread over
     // the block
-    __shared__ double s_m[16][kDMax];
+    __shared__ double s_m[16][DMAX];
     {
-        const int j = threadIdx.x & 15, g = threadIdx.x >> 4;
-        double v = 0.0;
-        if (j < nd) {
+        const int j = threadIdx.x & 15, g = threadIdx.x >> 4;   // NT >= 256: g covers 0..15
+        if (g < 16) {
+            double v = 0.0;
+            if (j < nd) {
 #pragma unroll 8
-            for (int blk = g; blk < (int)gridDim.x; blk += 16) v += p.partials[(int64_t)blk * nd + j];
+                for (int blk = g; blk < (int)gridDim.x; blk += 16)
+                    v += p.partials[(int64_t)blk * nd + j];
+            }
+            if (j < DMAX) s_m[g][j] = v;
         }
-        s_m[g][j] = v;
     }
     __syncthreads();
     if (threadIdx.x < nd) {
@@ -243,6 +321,27 @@ __global__ __launch_bounds__(kThreads) void k_diff_commit(const void* __restrict
 }
 
 // ---------------------------------------------------------------- dispatch
+
+// Block sizes: 16 waves per compute unit where the registers allow it
+// (up to 4 step sizes), 8 waves for 16 step sizes.
+constexpr int kEvalThreadsSmall = 1024;
+constexpr int kEvalThreadsLarge = 512;
+
+template <int DT>
+const void* diff_kernel_dt(int nd) {
+    if (nd <= 1) return reinterpret_cast<const void*>(&k_diff_eval<DT, 1, kEvalThreadsSmall>);
+    if (nd <= 4) return reinterpret_cast<const void*>(&k_diff_eval<DT, 4, kEvalThreadsSmall>);
+    return reinterpret_cast<const void*>(&k_diff_eval<DT, kDMax, kEvalThreadsLarge>);
+}
+
+const void* diff_kernel(int dtype, int nd) {
+    switch (dtype) {
+    case GLM_F64: return diff_kernel_dt<GLM_F64>(nd);
+    case GLM_F32: return diff_kernel_dt<GLM_F32>(nd);
+    case GLM_BF16: return diff_kernel_dt<GLM_BF16>(nd);
+    default: return diff_kernel_dt<GLM_FP8_E4M3>(nd);
+    }
+}
 
 int grid_for(const glm_ctx* ctx, int64_t N, int per_cu) {
     const int64_t need = (N + kThreads - 1) / kThreads;
@@ -393,7 +492,8 @@ glm_status glm_diff_logpost(glm_ctx* ctx, glm_dataset_id id, const double* u, co
     if (d.N > 0 && !u) GLM_FAIL(GLM_EINVAL, "glm_diff_logpost: u is NULL");
     st = use_device(ctx);
     if (st != GLM_OK) return st;
-    const int grid = grid_for(ctx, d.N, 4);
+    const int grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>(ctx->num_cu, (d.N + kEvalThreadsLarge * 4 - 1) / (kEvalThreadsLarge * 4)));
     Scratch* sc = nullptr;
     st = get_scratch(ctx, stream, (size_t)grid * kDMax, 0, 1, &sc);
     if (st != GLM_OK) return st;
@@ -416,12 +516,14 @@ glm_status glm_diff_logpost(glm_ctx* ctx, glm_dataset_id id, const double* u, co
         p.partials = sc->partials;
         p.ticket = sc->counters;
         p.family = d.family;
-        switch (d.dtype) {
-        case GLM_F64: hipLaunchKernelGGL(k_diff_eval<GLM_F64>, dim3(grid), dim3(kThreads), 0, s, p); break;
-        case GLM_F32: hipLaunchKernelGGL(k_diff_eval<GLM_F32>, dim3(grid), dim3(kThreads), 0, s, p); break;
-        case GLM_BF16: hipLaunchKernelGGL(k_diff_eval<GLM_BF16>, dim3(grid), dim3(kThreads), 0, s, p); break;
-        default: hipLaunchKernelGGL(k_diff_eval<GLM_FP8_E4M3>, dim3(grid), dim3(kThreads), 0, s, p); break;
-        }
+        const int es = elem_size(d.dtype);
+        p.vec = ((uintptr_t)p.col % (4 * es) == 0) && ((uintptr_t)u % 16 == 0) &&
+                ((uintptr_t)d.y % 4 == 0) &&
+                (d.dtype != GLM_F64 || (uintptr_t)p.col % 16 == 0);
+        const void* fn = diff_kernel(d.dtype, p.nd);
+        void* args[] = {&p};
+        const int nt = p.nd <= 4 ? kEvalThreadsSmall : kEvalThreadsLarge;
+        GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(grid), dim3(nt), args, 0, s));
         GLM_HIP_CHECK(hipGetLastError());
     }
     return GLM_OK;
