@@ -730,10 +730,88 @@ def bench_diff(args):
     return result
 
 
+def bench_sampler(args):
+    """Random-walk Metropolis with the whole chain on the device (glm_mh_run)
+    against the same chain driven from the host (one glm_logpost_grad_host
+    round trip and a host-side decision per step), on the 10,000 x 20 FP64
+    workload where the round trip dominates (paper Sec. 4.5), and on the
+    4M x 256 FP32 workload where the evaluation does."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    ctx = glm.glm_create(0)
+    out = {}
+    for name, w, n_dev, n_host, wi in (
+            ("small_n10000_k20_f64", synth.plain_small(1), max(args.steps, 2000), 1000, 0),
+            ("big_n4000000_k256_f32", synth.plain_big(n_evals=1), 200, 50, 1)):
+        N, K = w.X.shape
+        X = torch.from_numpy(w.X).to(dev)
+        y = torch.from_numpy(w.y).to(dev)
+        ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
+        prior = glm.make_prior(w.prec)
+        incs, logu, _ = synth.mh_chain_inputs(K, n_dev, N, workload_index=wi)
+        inc_d = torch.from_numpy(incs).to(dev)
+        lu_d = torch.from_numpy(logu).to(dev)
+        fg = torch.empty(K + 1, dtype=torch.float64, device=dev)
+        acc = torch.empty(n_dev, dtype=torch.uint8, device=dev)
+        # warm-up (plans, scratch)
+        b = torch.from_numpy(w.beta_true.copy()).to(dev)
+        glm.glm_mh_run(ctx, ds, b, fg, inc_d, lu_d, min(20, n_dev), prior, acc)
+        torch.cuda.synchronize()
+        b = torch.from_numpy(w.beta_true.copy()).to(dev)
+        t0 = time.perf_counter()
+        glm.glm_mh_run(ctx, ds, b, fg, inc_d, lu_d, n_dev, prior, acc)
+        torch.cuda.synchronize()
+        dev_s = time.perf_counter() - t0
+        dev_acc = acc.cpu().numpy()
+        # host-driven: the same increments and uniforms
+        beta = w.beta_true.copy()
+        f_cur = glm.glm_logpost_grad_host(ctx, ds, beta, prior)
+        host_acc = np.empty(n_host, np.uint8)
+        t0 = time.perf_counter()
+        for t in range(n_host):
+            bp = beta + incs[t]
+            fp = glm.glm_logpost_grad_host(ctx, ds, bp, prior)
+            host_acc[t] = logu[t] < fp - f_cur
+            if host_acc[t]:
+                beta, f_cur = bp, fp
+        host_s = time.perf_counter() - t0
+        out[name] = {"device_steps_per_s": n_dev / dev_s, "device_us_per_step": dev_s / n_dev * 1e6,
+                     "host_steps_per_s": n_host / host_s, "host_us_per_step": host_s / n_host * 1e6,
+                     "speedup": (n_dev / dev_s) / (n_host / host_s),
+                     "accept_rate": float(dev_acc.mean()),
+                     "decisions_equal_host_driven": bool(np.array_equal(dev_acc[:n_host], host_acc)),
+                     "steps_device": n_dev, "steps_host": n_host}
+        print(f"[bench] sampler {name}: {out[name]}", file=sys.stderr, flush=True)
+        glm.glm_dataset_unregister(ctx, ds)
+        del X, y
+    glm.glm_destroy(ctx)
+    sm = out["small_n10000_k20_f64"]
+    return {
+        "metric": "random-walk Metropolis steps/s with the chain on the device (one fused "
+                  "f+g evaluation per step)",
+        "value": sm["device_steps_per_s"], "unit": "steps/s", "n_gpus": 1,
+        "steps": sm["steps_device"], "warmup": 20, "ms_per_step": sm["device_us_per_step"] * 1e-3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "on-device Metropolis: N=10,000 K=20 FP64 (and N=4,000,000 K=256 "
+                               "FP32), proposal sd 2.38/sqrt(K)/sqrt(0.2 N)"},
+        "roofline": {"bound": "latency", "achieved": None, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": None, "traffic": None,
+                     "note": "the small workload is bound by launch latency, not HBM"},
+        "workloads": out,
+    }
+
+
 WORKLOADS = {"copy": bench_copy, "plain_big": bench_plain_big, "precision": bench_precision,
              "batched": bench_batched, "plain_small": bench_plain_small,
              "serving": bench_serving, "diff": bench_diff,
-             "poisson": lambda a: bench_plain_big(a, poisson=True)}
+             "poisson": lambda a: bench_plain_big(a, poisson=True),
+             "sampler": bench_sampler}
 
 
 def main() -> int:

@@ -401,6 +401,26 @@ glm_status glm_diff_logpost(glm_ctx* ctx, glm_dataset_id colset, const double* u
 glm_status glm_diff_commit(glm_ctx* ctx, glm_dataset_id colset, double* u, double* beta,
                            int32_t k, const double* delta, void* stream);
 
+/* ------------------------------------------------ on-device sampler loop */
+
+/* Runs n_steps of random-walk Metropolis on the device without host
+ * round trips (Sec. 4.5 measures the round trip that this removes; the
+ * accept rule is the Metropolis step of Sec. 2.2):
+ *   beta' = beta + incs[t*K .. t*K+K-1];  accept iff logu[t] < f(beta') - f(beta)
+ * All pointers are device pointers.  beta (K doubles) is the starting point
+ * on entry and the chain's last state on return; fg (1 + K doubles) receives
+ * f and g at the last state.  incs (n_steps x K) and logu (n_steps) are the
+ * proposal increments and log-uniforms, drawn by the caller.  accepted
+ * (n_steps bytes, 0/1) and f_trace (n_steps doubles: f of the state after
+ * step t) may be NULL.  Async on `stream`; the kernels run in stream order,
+ * one fused evaluation per step.  Chains on different streams are
+ * independent; two calls on one stream must not overlap in time from
+ * different host threads.  Errors: GLM_EINVAL, GLM_ENOTFOUND, GLM_ENOMEM,
+ * GLM_EHIP. */
+glm_status glm_mh_run(glm_ctx* ctx, glm_dataset_id id, double* beta, double* fg,
+                      const double* incs, const double* logu, int32_t n_steps,
+                      const glm_prior* prior, uint8_t* accepted, double* f_trace, void* stream);
+
 /* -------------------------------------------------------- boundary probe */
 
 /* The offload round trip the paper measures on its GPU (Sec. 4.5): copy K

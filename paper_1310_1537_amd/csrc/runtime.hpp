@@ -85,6 +85,13 @@ struct Scratch {
     size_t cap_counters = 0;   // unsigned
 };
 
+// Device chain state of the on-device sampler for one stream: the proposal,
+// f and g at the proposal, and the step counter.
+struct SamplerBuf {
+    double* buf = nullptr;
+    size_t cap = 0;        // doubles
+};
+
 struct GroupSet;   // defined by the batched entry point
 
 }  // namespace glmrt
@@ -98,6 +105,7 @@ struct glm_ctx {
     std::unordered_map<int64_t, glmrt::Dataset> datasets;
     std::unordered_map<int64_t, glmrt::ColSet> colsets;
     std::map<void*, glmrt::Scratch> scratch;   // keyed by stream
+    std::map<void*, glmrt::SamplerBuf> sampler;  // keyed by stream
     hipStream_t own_stream = nullptr;
     // host-call staging (pinned) and device buffers
     double* h_stage = nullptr;

@@ -115,6 +115,7 @@ _SIGS = {
     "glm_linpred": [_P, _I64, _P, _P, _P],
     "glm_diff_logpost": [_P, _I64, _P, _P, _I32, _P, _I32, ctypes.POINTER(glm_prior), _P, _P],
     "glm_diff_commit": [_P, _I64, _P, _P, _I32, _P, _P],
+    "glm_mh_run": [_P, _I64, _P, _P, _P, _P, _I32, ctypes.POINTER(glm_prior), _P, _P, _P],
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_probe_read_bandwidth": [_P, _P, _I64, _I32, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
@@ -299,6 +300,15 @@ def glm_diff_logpost(ctx: int, cs: int, u, beta, k: int, deltas, nd: int, prior:
 
 def glm_diff_commit(ctx: int, cs: int, u, beta, k: int, delta, stream=None) -> None:
     _check(_lib.glm_diff_commit(ctx, cs, _ptr(u), _ptr(beta), k, _ptr(delta), _stream(stream)))
+
+
+# ---------------------------------------------------------------- on-device sampler
+
+def glm_mh_run(ctx: int, ds: int, beta, fg, incs, logu, n_steps: int, prior: glm_prior,
+               accepted=None, f_trace=None, stream=None) -> None:
+    """Random-walk Metropolis on the device (all arguments device tensors)."""
+    _check(_lib.glm_mh_run(ctx, ds, _ptr(beta), _ptr(fg), _ptr(incs), _ptr(logu), n_steps,
+                           ctypes.byref(prior), _ptr(accepted), _ptr(f_trace), _stream(stream)))
 
 
 # ---------------------------------------------------------------- batched
