@@ -27,22 +27,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fg_fused_plain_big_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
-def kernel_source_hash() -> str:
-    from paper_1310_1537_amd.profiling import kernel_source_hash as h
-    return h()
-
-
-def measured_traffic(bytes_alg: float):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+def measured_traffic(name: str, kind: str = "plain"):
+    """HBM bytes per launch from the committed rocprofv3 counter runs
+    (profiles/<name>_traffic.json), if they were taken on the current kernel
+    sources; else None."""
+    from paper_1310_1537_amd.profiling import kernel_source_hash
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(os.path.join(PROFILES, name + "_traffic.json")))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(kind):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -168,7 +165,7 @@ def bench_plain_big(args, poisson: bool = False):
                    "N": N, "K": K, "storage": "fp32", "result": "fp64", "prior_sd": 10},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS,
-                     "traffic": None if poisson else measured_traffic(bytes_alg),
+                     "traffic": None if poisson else measured_traffic("fg_fused_plain_big"),
                      "kernel": "fg_fused<f32, 64 lanes/row>", "bytes_per_launch": bytes_alg,
                      "launch_us_avg": avg_ms * 1e3,
                      "read_ceiling_GBps": ceiling, "frac_of_read_ceiling": achieved / ceiling},
@@ -276,7 +273,8 @@ def bench_precision(args):
                                      args.warmup, args.steps, stream)
         bytes_alg = float(N) * K * es + N
         avg = float(kern_ms.mean())
-        formats[name] = {"evals_per_s": args.steps / wall, "launch_us_avg": avg * 1e3,
+        formats[name] = {"traffic": measured_traffic(f"fg_fused_precision_{name}"),
+                         "evals_per_s": args.steps / wall, "launch_us_avg": avg * 1e3,
                          "GBps": bytes_alg / (avg * 1e-3) / 1e9,
                          "frac_peak": bytes_alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS,
                          "bytes_per_launch": bytes_alg, "first_out": outs[0].cpu().numpy()}
@@ -303,7 +301,8 @@ def bench_precision(args):
         "config": {"workload": f"precision: N={N} K={K}, X as FP32 / BF16 / FP8-E4M3 "
                                "(per-column scales), same trajectory", "N": N, "K": K},
         "roofline": {"bound": "hbm", "achieved": b["GBps"], "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": b["frac_peak"], "traffic": None},
+                     "unit": "GB/s", "frac": b["frac_peak"],
+                     "traffic": measured_traffic("fg_fused_precision_bf16")},
         "formats": formats,
     }
     if not args.no_cpu_baseline:
@@ -404,10 +403,11 @@ def bench_batched(args):
         "group_evals_per_s": G * steps / wall,
         "roofline": {"bound": "hbm", "achieved": bytes_alg / (avg * 1e-3) / 1e9,
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": bytes_alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS, "traffic": None,
+                     "frac": bytes_alg / (avg * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+                     "traffic": measured_traffic("fg_batched_hierarchical", "batched"),
                      "bytes_per_launch": bytes_alg, "launch_us_avg": avg * 1e3,
                      "note": "X is 263 MB, about the 256 MB Infinity Cache: repeated steps "
-                             "may be served partly from it"},
+                             "may be served partly from it (traffic counts what left L2)"},
         "schedule": info, "groupset_create_s": t_create,
         "plain_per_group": {"ms_per_step": wall_plain * 1e3,
                             "speedup_of_batched": wall_plain / (wall / steps)},
@@ -698,7 +698,8 @@ def bench_diff(args):
                                "copy), one coefficient per step, nd candidate moves per pass",
                    "N": N, "K": K},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS,
+                     "traffic": measured_traffic("k_diff_eval_diff_update", "diff"),
                      "bytes_per_launch": eval_bytes, "launch_us_avg": r1["eval_us_avg"],
                      "note": "column k is new each step; u (32 MB) and y (4 MB) are re-read "
                              "every step and may be served from the 256 MB Infinity Cache"},
@@ -807,11 +808,76 @@ def bench_sampler(args):
     }
 
 
+def bench_hessian(args):
+    """f, g and the Hessian H = -X^t W X - prec I fused (paper Sec. 5.2) on
+    the 4M x 256 FP32 workload: FP64 matrix-core contraction over the rows."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    w = synth.plain_big(n_evals=max(args.steps, 1) + args.warmup)
+    N, K = w.X.shape
+    X = torch.from_numpy(w.X).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    ctx = glm.glm_create(0)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
+    prior = glm.make_prior(w.prec)
+    betas = torch.from_numpy(np.ascontiguousarray(w.betas)).to(dev)
+    out = torch.empty(K + 1, dtype=torch.float64, device=dev)
+    H = torch.empty((K, K), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        glm.glm_logpost_grad_hess(ctx, ds, betas[i], prior, out, H, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for j in range(args.steps):
+        a, b = ev[j]
+        a.record(stream)
+        glm.glm_logpost_grad_hess(ctx, ds, betas[args.warmup + j], prior, out, H, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    # the f+g part alone, for the split
+    f_ms = []
+    for j in range(min(args.steps, 20)):
+        a, b = ev[j]
+        a.record(stream)
+        glm.glm_logpost_grad(ctx, ds, betas[j], prior, out, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        f_ms.append(a.elapsed_time(b))
+    glm.glm_dataset_unregister(ctx, ds)
+    glm.glm_destroy(ctx)
+    avg = float(ms.mean())
+    fg_avg = float(np.mean(f_ms))
+    flops = float(N) * K * (K + 1)          # the symmetric contraction, multiply-adds x 2
+    h_ms = max(avg - fg_avg, 1e-6)
+    return {
+        "metric": "f + g + Hessian evals/s (FP64 Hessian on the matrix cores)",
+        "value": args.steps / wall, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Hessian: N=4,000,000 K=256 FP32 X, random-walk trajectory",
+                   "N": N, "K": K},
+        "roofline": {"bound": "mfma", "achieved": flops / (h_ms * 1e-3) / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": flops / (h_ms * 1e-3) / 1e12 / 78.6,
+                     "traffic": None, "flops_per_launch": flops,
+                     "note": "Hessian kernel time = (f+g+H call) - (f+g call), FP64 MFMA peak"},
+        "ms_per_call": avg, "fg_ms": fg_avg, "hessian_kernel_ms": h_ms,
+    }
+
+
 WORKLOADS = {"copy": bench_copy, "plain_big": bench_plain_big, "precision": bench_precision,
              "batched": bench_batched, "plain_small": bench_plain_small,
              "serving": bench_serving, "diff": bench_diff,
              "poisson": lambda a: bench_plain_big(a, poisson=True),
-             "sampler": bench_sampler}
+             "sampler": bench_sampler, "hessian": bench_hessian}
 
 
 def main() -> int:

@@ -338,6 +338,21 @@ glm_status glm_server_shutdown(glm_server* srv);
 /* Shuts down (if needed) and frees the server and its device copies. */
 glm_status glm_server_destroy(glm_server* srv);
 
+/* --------------------------------------------------------------- Hessian */
+
+/* f, g and the Hessian H = -X^t W X - prec I at one beta (the paper names the
+ * Hessian as the next derivative to fuse, Sec. 5.2), W = diag(w_n) with
+ * w_n = sigmoid(u_n)(1 - sigmoid(u_n)) for GLM_LOGISTIC and exp(u_n) for
+ * GLM_POISSON.  Device pointers: beta (K), prior mean as for
+ * glm_logpost_grad, out (1 + K: f then g, as glm_logpost_grad), H (K x K
+ * doubles, row-major, symmetric).  H is computed on the matrix cores in FP64
+ * (products and sums) from each row's w_n, which the fused f+g pass writes;
+ * the library keeps per-stream buffers of N + O(K^2) doubles for that.
+ * Async on `stream`; bitwise reproducible.  Errors: GLM_EINVAL,
+ * GLM_ENOTFOUND, GLM_ENOMEM, GLM_EHIP. */
+glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* beta,
+                                 const glm_prior* prior, double* out, double* H, void* stream);
+
 /* ----------------------------------------------- differential update */
 
 /* One-coefficient-at-a-time samplers (slice sampling or Gibbs over the

@@ -53,6 +53,7 @@ def lib():
         L.orc_logpost_grad.argtypes = [P, I, I64, P, P, I64, I, P, D, P, I, P]
         L.orc_logpost_grad_multi.argtypes = [P, I, I64, P, P, I64, I, P, I, D, P, I, P]
         L.orc_linpred.argtypes = [P, I, I64, P, I64, I, P, P]
+        L.orc_hessian.argtypes = [P, I, I64, P, I64, I, P, D, I, P]
         L.orc_logpost_grad_groups.argtypes = [P, I, I64, P, P, P, I, I, P, D, P, I, I, P]
         L.orc_quantize_bf16.argtypes = [P, I64, I, I64, P, I64]
         L.orc_fp8_col_scales.argtypes = [P, I64, I, I64, P]
@@ -120,6 +121,19 @@ def linpred(X, beta, dtype=None, scale=None):
     if lib().orc_linpred(_p(X), code, ldx, _p(scale), N, K, _p(beta), _p(u)):
         raise ValueError("oracle rejected its arguments")
     return u
+
+
+def hessian(X, beta, prec, dtype=None, scale=None, family="logistic"):
+    """H = -X^t W X - prec I at beta (K x K, FP64)."""
+    code, ldx, X = _xinfo(X, dtype)
+    N, K = X.shape
+    beta = np.ascontiguousarray(beta, np.float64)
+    scale = None if scale is None else np.ascontiguousarray(scale, np.float32)
+    H = np.empty((K, K))
+    if lib().orc_hessian(_p(X), code, ldx, _p(scale), N, K, _p(beta), float(prec),
+                         FAMILIES[family], _p(H)):
+        raise ValueError("oracle rejected its arguments")
+    return H
 
 
 def logpost_grad_multi(X, y, betas, prec, means=None, dtype=None, scale=None, family="logistic"):

@@ -180,6 +180,42 @@ int orc_linpred(const void* X, int dtype, int64_t ldx, const float* scale, int64
     return 0;
 }
 
+/* Hessian of f: H = -sum_n w_n x_n x_n^t - prec I, with the per-row weight
+ * w_n = -d^2 t_n / du^2 = sigmoid(u)(1 - sigmoid(u)) (logistic) or exp(u)
+ * (Poisson).  Every entry is a Neumaier-compensated sum over n in ascending
+ * order; H is K x K row-major (both triangles written). */
+int orc_hessian(const void* X, int dtype, int64_t ldx, const float* scale, int64_t N, int K,
+                const double* beta, double prec, int family, double* H) {
+    if (K < 1 || N < 0 || ldx < K || !beta || !H) return -1;
+    if (family != ORC_LOGISTIC && family != ORC_POISSON) return -1;
+    if (N > 0 && !X) return -1;
+    nsum* acc = (nsum*)calloc((size_t)K * K, sizeof(nsum));
+    double* x = (double*)malloc((size_t)K * sizeof(double));
+    if (!acc || !x) { free(acc); free(x); return -1; }
+    for (int64_t n = 0; n < N; ++n) {
+        double u = 0.0;
+        for (int k = 0; k < K; ++k) {
+            x[k] = elem(X, dtype, n * ldx + k, scale, k);
+            u += x[k] * beta[k];
+        }
+        double w;
+        if (family == ORC_LOGISTIC) {
+            double s = orc_sigmoid(u);
+            w = s * (1.0 - s);
+        } else {
+            w = exp(u);
+        }
+        for (int i = 0; i < K; ++i)
+            for (int j = 0; j < K; ++j) nsum_add(&acc[(size_t)i * K + j], w * x[i] * x[j]);
+    }
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j)
+            H[(size_t)i * K + j] = -nsum_get(&acc[(size_t)i * K + j]) - (i == j ? prec : 0.0);
+    free(acc);
+    free(x);
+    return 0;
+}
+
 /* Several evaluation points on one data set: betas and out are b x K and
  * b x (1 + K), row-major; means is b x K or NULL. */
 int orc_logpost_grad_multi(const void* X, int dtype, int64_t ldx, const float* scale,

@@ -79,6 +79,7 @@ struct FgParams {
     int group;                // blocks per merge group
     int interleave;           // 1: wave w takes batches w, w+W, ...; 0: one contiguous range
     int family;               // response family (0 logistic, 1 Poisson)
+    double* w_out;            // N Hessian row weights, or nullptr (NB == 1 only)
 };
 
 // ------------------------------------------------------------ decoding
@@ -247,6 +248,16 @@ __device__ __forceinline__ void tr_map(double u, unsigned yb, int fam, double& t
     r = yv - sig;
 }
 
+// Row weight of the Hessian (minus the second derivative of t in u):
+// sigmoid(u) (1 - sigmoid(u)) = e / (1 + e)^2 with e = exp(-|u|) for the
+// logistic model, exp(u) for the Poisson one.
+__device__ __forceinline__ double tr_weight(double u, int fam) {
+    if (fam == 1) return exp_f64(u);
+    const double e = exp_f64(-fabs(u));
+    const double inv = 1.0 / (1.0 + e);
+    return e * inv * inv;
+}
+
 // ------------------------------------------------------------ finalisation
 
 // sum_{t < n} a[t * stride] in index order, with 16 loads in flight: the
@@ -372,6 +383,7 @@ struct WaveTile {
 
     int lane, seg, cl, NC, KC;
     int fam;                 // response family (wave-uniform)
+    double* wout = nullptr;  // per-row Hessian weights of slot 0, or nullptr
     bool ragged;             // K * ES is not a whole number of chunks (wave-uniform)
     u32x4 xmask[CPL];        // bytes of chunk i that are columns < K (ragged K only)
     uint32_t ldb;            // row stride in bytes
@@ -485,7 +497,7 @@ struct WaveTile {
     // skipped, so a partly filled pass costs what it carries).  rbuf: this
     // wave's LDS slice of RBUF values.
     __device__ __forceinline__ void compute(Tile& t, uint32_t nvalid, rtype* rbuf,
-                                            int nact = NB) {
+                                            int nact = NB, int64_t row0 = 0) {
         if (ragged) {
 #pragma unroll
             for (int j = 0; j < R; ++j)
@@ -542,6 +554,8 @@ struct WaveTile {
                 tr_map(uo[o], t.yb[o], fam, tt, rr);
                 const bool ok = yoff[o] < nvalid;
                 if (ok && unique) facc[b] += tt;
+                if (b == 0 && wout != nullptr && ok && unique)
+                    wout[row0 + yoff[o]] = tr_weight(uo[o], fam);
                 if (unique) {
                     const int j = R >= LPR ? cl * OWN + o : cl / REP;
                     rbuf[(b * RPW + seg) * R + j] = ok ? (rtype)rr : (rtype)0;
@@ -602,10 +616,10 @@ struct WaveTile {
         load(ta, X, y, r0, r1 - r0);
         for (int64_t b = r0; b < r1; b += 2 * BATCH) {
             load(tb, X, y, b + BATCH, r1 - b - BATCH);
-            compute(ta, (uint32_t)min((int64_t)BATCH, r1 - b), rbuf, nact);
+            compute(ta, (uint32_t)min((int64_t)BATCH, r1 - b), rbuf, nact, b);
             if (b + BATCH >= r1) break;
             load(ta, X, y, b + 2 * BATCH, r1 - b - 2 * BATCH);
-            compute(tb, (uint32_t)min((int64_t)BATCH, r1 - b - BATCH), rbuf, nact);
+            compute(tb, (uint32_t)min((int64_t)BATCH, r1 - b - BATCH), rbuf, nact, b + BATCH);
         }
     }
 
@@ -638,6 +652,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     // wave-uniform: keeps the batch bookkeeping and buffer bases in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     wt.init(threadIdx.x & 63, p.K, p.ldx, p.family);
+    if constexpr (NB == 1) wt.wout = p.w_out;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         if (b < p.nb) {
@@ -671,10 +686,12 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
         wt.load(ta, p.X, p.y, r, p.N - r);
         for (; r < rend; r += 2 * step) {
             wt.load(tb, p.X, p.y, r + step, p.N - r - step);
-            wt.compute(ta, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r)), rbuf[wave], nact);
+            wt.compute(ta, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r)), rbuf[wave], nact,
+                       r);
             if (r + step >= rend) break;
             wt.load(ta, p.X, p.y, r + 2 * step, p.N - r - 2 * step);
-            wt.compute(tb, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r - step)), rbuf[wave], nact);
+            wt.compute(tb, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r - step)), rbuf[wave],
+                       nact, r + step);
         }
     } else {
         const int64_t r0 = min(p.N, nbatch * gw / tw * BATCH);

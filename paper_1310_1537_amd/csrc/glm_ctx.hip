@@ -169,6 +169,8 @@ glm_status glm_destroy(glm_ctx* ctx) {
         if (kv.second.base) hipFree(kv.second.base);
     for (auto& kv : ctx->sampler)
         if (kv.second.buf) hipFree(kv.second.buf);
+    for (auto& kv : ctx->hess)
+        if (kv.second.buf) hipFree(kv.second.buf);
     if (ctx->h_stage) hipHostFree(ctx->h_stage);
     if (ctx->d_stage) hipFree(ctx->d_stage);
     if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);

@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "runtime.hpp"
+#include "elem.hpp"
 #include "tr_math.hpp"
 
 namespace glmrt {
@@ -33,33 +34,6 @@ namespace {
 
 constexpr int kDMax = 16;       // step sizes per pass
 constexpr int kThreads = 256;
-
-// ---------------------------------------------------------------- elements
-
-template <int DT> struct Elem;
-template <> struct Elem<GLM_F64> {
-    using T = double;
-    static __device__ __forceinline__ double value(T v, float) { return v; }
-};
-template <> struct Elem<GLM_F32> {
-    using T = float;
-    static __device__ __forceinline__ double value(T v, float) { return (double)v; }
-};
-template <> struct Elem<GLM_BF16> {
-    using T = unsigned short;
-    static __device__ __forceinline__ double value(T v, float) {
-        return (double)__uint_as_float((unsigned)v << 16);
-    }
-};
-template <> struct Elem<GLM_FP8_E4M3> {
-    using T = unsigned char;
-    static __device__ __forceinline__ double value(T v, float s) {
-        // native OCP E4M3FN conversion; the code times its column scale is
-        // exact in FP64
-        const float x = __builtin_amdgcn_cvt_pk_f32_fp8((int)v, false)[0];
-        return (double)x * (double)s;
-    }
-};
 
 // t(v) = y v - b(v) with b the log-partition of the response family:
 // softplus (logistic) or exp (Poisson, y a count).
@@ -100,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_linpred(const void* __restrict__ X
                                                       const float* __restrict__ scale, int64_t N,
                                                       int K, const double* __restrict__ beta,
                                                       double* __restrict__ u) {
-    using E = Elem<DT>;
+    using E = glmk::Elem<DT>;
     const typename E::T* Xt = static_cast<const typename E::T*>(Xt_);
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += stride) {
@@ -181,7 +155,7 @@ __device__ __forceinline__ void load4(const void* col, int64_t n0, float s, doub
 template <int DT, int DMAX, int NT>
 __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
     static_assert(NT >= 256 && NT % 64 == 0, "the final merge uses 16 x 16 lanes");
-    using E = Elem<DT>;
+    using E = glmk::Elem<DT>;
     const typename E::T* col = static_cast<const typename E::T*>(p.col);
     const int nd = p.nd;
     const int fam = p.family;
@@ -311,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_diff_commit(const void* __restrict
                                                           int64_t N, const double* __restrict__ delta,
                                                           double* __restrict__ u,
                                                           double* __restrict__ beta, int k) {
-    using E = Elem<DT>;
+    using E = glmk::Elem<DT>;
     const typename E::T* col = static_cast<const typename E::T*>(col_);
     const double dl = *delta;
     const int64_t stride = (int64_t)gridDim.x * kThreads;

@@ -1,0 +1,282 @@
+// Log-posterior Hessian fused with f and g:
+//
+//     H = -X^t W X - prec I,   W = diag(w_n),
+//     w_n = sigmoid(u_n) (1 - sigmoid(u_n))  (logistic),  exp(u_n)  (Poisson).
+//
+// The paper names the Hessian as the next quantity to add to the fused
+// routine (Sec. 5.2; Hessian-based samplers and optimisers are listed in
+// Sec. 4.2).  X^t W X is a dense contraction over the rows, so it runs on the
+// matrix cores: FP64 MFMA (v_mfma_f64_16x16x4), products and sums in FP64.
+//
+// Three launches in stream order:
+//   1. the fused f+g kernel, which also writes each row's w_n (N doubles);
+//   2. k_hess: the K x K output is cut into 128 x 128 tiles, of which the
+//      upper triangle (tile row <= tile column) is computed; the rows are cut
+//      into S chunks; block (tile, chunk) stages 32 rows of the tile's column
+//      ranges (and w) into LDS as doubles and its four waves each accumulate
+//      a 64 x 64 quadrant with 4 x 4 MFMA blocks, four rows per instruction,
+//      and write the block's partial tile;
+//   3. k_hess_merge: one thread per tile entry adds the S partials in chunk
+//      order and writes the entry and its mirror image, minus prec on the
+//      diagonal.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "elem.hpp"
+#include "runtime.hpp"
+
+namespace glmrt {
+namespace {
+
+constexpr int kTile = 128;    // output tile edge
+constexpr int kRows = 32;     // rows staged per step
+constexpr int kHT = 256;      // threads per block (4 waves)
+constexpr int kPer = kRows * 2 * kTile / kHT;   // staged elements per thread (off-diagonal tile)
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+struct HessParams {
+    const void* X;
+    int64_t ldx;
+    const float* scale;       // FP8 column scales
+    const double* w;          // N row weights
+    int64_t N;
+    int K;
+    int nchunk;               // row chunks
+    const int2* tiles;        // (tile row, tile column) of each upper-triangle tile
+    double* partials;         // ntiles_upper x nchunk x kTile x kTile
+};
+
+// Block (tile, chunk): sum over the chunk's rows of w_n x_n,i x_n,j for the
+// tile's 128 x 128 entries; each wave owns a 64 x 64 quadrant (4 x 4 MFMA
+// blocks of 16 x 16).  Rows are staged kRows at a time; the next rows'
+// elements are loaded into registers while the matrix cores work on the
+// current ones.  Every thread stages one fixed column (thread t takes column
+// t mod width, rows t / width + q * 256 / width).
+template <int DT>
+__global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
+    using E = glmk::Elem<DT>;
+    const typename E::T* X = static_cast<const typename E::T*>(p.X);
+    const int tile = blockIdx.x / p.nchunk;
+    const int chunk = blockIdx.x % p.nchunk;
+    const int2 tc = p.tiles[tile];
+    const int i0 = tc.x * kTile, j0 = tc.y * kTile;
+    const bool diag = tc.x == tc.y;
+    const int64_t r0 = p.N * chunk / p.nchunk;
+    const int64_t r1 = p.N * (chunk + 1) / p.nchunk;
+
+    // xs[r][c]: c < kTile the i-range, c >= kTile the j-range (off-diagonal tiles)
+    __shared__ double xs[kRows][2 * kTile + 1];
+    __shared__ double ws[kRows];
+
+    const int width = diag ? kTile : 2 * kTile;       // staged columns
+    const int nper = kRows * width / kHT;              // staged elements per thread
+    const int sc = threadIdx.x % width;                // this thread's staged column
+    const int srow = threadIdx.x / width;              // first staged row
+    const int rstep = kHT / width;
+    const int col = sc < kTile ? i0 + sc : j0 + (sc - kTile);
+    const bool col_ok = col < p.K;
+    const float cs = (DT == GLM_FP8_E4M3 && col_ok) ? p.scale[col] : 1.0f;
+
+    // Loads are issued unconditionally from clamped (always valid) addresses
+    // and masked afterwards, so that they are all in flight at once.
+    const int colc = col_ok ? col : p.K - 1;
+    double v[kPer];
+    double wv = 0.0;
+    auto fetch = [&](int64_t r) {
+        typename E::T raw[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t row = min(r + srow + q * rstep, r1 - 1);
+            raw[q] = X[row * p.ldx + colc];
+        }
+        const double wl = p.w[min(r + (int64_t)(threadIdx.x % kRows), r1 - 1)];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t row = r + srow + q * rstep;
+            v[q] = (col_ok && row < r1 && q < nper) ? E::value(raw[q], cs) : 0.0;
+        }
+        wv = r + (int64_t)(threadIdx.x % kRows) < r1 ? wl : 0.0;
+    };
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int qi = (wave >> 1) * 64, qj = (wave & 1) * 64;   // this wave's quadrant
+    const int jb = diag ? 0 : kTile;
+    dv4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = dv4{0.0, 0.0, 0.0, 0.0};
+
+    if (r0 < r1) fetch(r0);
+    for (int64_t r = r0; r < r1; r += kRows) {
+        __syncthreads();   // the previous step's MFMA reads of xs are done
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            if (q >= nper) break;
+            xs[srow + q * rstep][sc] = v[q];
+        }
+        if (threadIdx.x < kRows) ws[threadIdx.x] = wv;
+        __syncthreads();
+        if (r + kRows < r1) fetch(r + kRows);
+#pragma unroll
+        for (int k0 = 0; k0 < kRows; k0 += 4) {
+            // A[i][k] = w_k x_k,(i0+i), B[k][j] = x_k,(j0+j); lane: i or j = lane % 16, k = lane / 16
+            const int kk = k0 + (lane >> 4);
+            const double wk = ws[kk];
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = wk * xs[kk][qi + 16 * t + (lane & 15)];
+                b[t] = xs[kk][jb + qj + 16 * t + (lane & 15)];
+            }
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < 4; ++tb)
+                    acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+        }
+    }
+
+    // partial tile: D[row][col] of a 16 x 16 block sits in lane col + 16 (row % 4), item row / 4
+    double* part = p.partials + (int64_t)blockIdx.x * kTile * kTile;
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = qi + 16 * ta + (lane >> 4) + 4 * q;
+                const int j = qj + 16 * tb + (lane & 15);
+                part[i * kTile + j] = acc[ta][tb][q];
+            }
+}
+
+// H entries from the partials: each thread sums one tile entry over the
+// chunks in chunk order; on a diagonal tile only i <= j is taken and mirrored,
+// so H is exactly symmetric.
+__global__ __launch_bounds__(kHT) void k_hess_merge(const double* __restrict__ partials,
+                                                    const int2* __restrict__ tiles, int nchunk,
+                                                    int K, double prec, double* __restrict__ H) {
+    const int64_t e_all = (int64_t)blockIdx.x * kHT + threadIdx.x;
+    const int tile = (int)(e_all / (kTile * kTile));
+    const int e = (int)(e_all % (kTile * kTile));
+    const int2 tc = tiles[tile];
+    const int i = e / kTile, j = e % kTile;
+    const int gi = tc.x * kTile + i, gj = tc.y * kTile + j;
+    const bool diag = tc.x == tc.y;
+    if (gi >= K || gj >= K || (diag && i > j)) return;
+    const double* base = partials + (int64_t)tile * nchunk * kTile * kTile + e;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c + u < nchunk ? base[(int64_t)(c + u) * kTile * kTile] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    const double h = -s - (gi == gj ? prec : 0.0);
+    H[(int64_t)gi * K + gj] = h;
+    if (gi != gj) H[(int64_t)gj * K + gi] = h;
+}
+
+}  // namespace
+}  // namespace glmrt
+
+using namespace glmrt;
+
+extern "C" {
+
+glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* beta,
+                                 const glm_prior* prior, double* out, double* H, void* stream) {
+    clear_error();
+    if (!ctx || !beta || !prior || !out || !H)
+        GLM_FAIL(GLM_EINVAL, "glm_logpost_grad_hess: NULL argument");
+    if (!(prior->prec >= 0.0)) GLM_FAIL(GLM_EINVAL, "glm_logpost_grad_hess: prior precision < 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->datasets.find(id);
+    if (it == ctx->datasets.end())
+        GLM_FAIL(GLM_ENOTFOUND, "glm_logpost_grad_hess: unknown data set %lld", (long long)id);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    const Dataset& ds = it->second;
+    const int K = ds.d.K;
+    const int64_t N = ds.d.N;
+    hipStream_t s = (hipStream_t)stream;
+
+    const int ntile = (K + kTile - 1) / kTile;
+    const int nup = ntile * (ntile + 1) / 2;
+    const int nchunk = (int)std::max<int64_t>(
+        1, std::min<int64_t>((2 * (int64_t)ctx->num_cu + nup - 1) / nup, (N + kRows - 1) / kRows));
+
+    // per-stream buffers: w (N), partials, tile list
+    HessBuf& hb = ctx->hess[stream];
+    const size_t need = (size_t)std::max<int64_t>(N, 1) + (size_t)nup * nchunk * kTile * kTile +
+                        (size_t)nup + 1;   // doubles (the tile list follows)
+    if (hb.cap < need || hb.ntick < (size_t)nup) {
+        if (hb.buf) {
+            GLM_HIP_CHECK(hipStreamSynchronize(s));
+            GLM_HIP_CHECK(hipFree(hb.buf));
+            hb = HessBuf{};
+        }
+        const size_t cap = need * 5 / 4 + 1024;
+        const size_t nt = std::max<size_t>((size_t)nup * 2, 64);
+        if (hipMalloc((void**)&hb.buf, cap * sizeof(double) + nt * sizeof(int2)) != hipSuccess)
+            GLM_FAIL(GLM_ENOMEM, "glm_logpost_grad_hess: device allocation failed");
+        hb.cap = cap;
+        hb.ntick = nt;
+        hb.tiles = reinterpret_cast<int*>(hb.buf + cap);
+        hb.tiles_for = -1;
+    }
+    double* w = hb.buf;
+    double* partials = hb.buf + std::max<int64_t>(N, 1);
+    if (hb.tiles_for != ntile) {
+        std::vector<int> t;
+        for (int a = 0; a < ntile; ++a)
+            for (int b = a; b < ntile; ++b) {
+                t.push_back(a);
+                t.push_back(b);
+            }
+        GLM_HIP_CHECK(hipMemcpyAsync(hb.tiles, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        GLM_HIP_CHECK(hipStreamSynchronize(s));
+        hb.tiles_for = ntile;
+    }
+
+    // 1. f, g and the row weights
+    size_t np, ng, nc;
+    scratch_need(ds.plan, K, 1, &np, &ng, &nc);
+    Scratch* sc = nullptr;
+    st = get_scratch(ctx, stream, np, ng, nc, &sc);
+    if (st != GLM_OK) return st;
+    st = launch_fused(ds.d, ds.plan, ds.plan.fn, 1, beta, prior->mean, nullptr, prior->prec, 1, out,
+                      sc, s, w);
+    if (st != GLM_OK) return st;
+
+    // 2. H = -X^t W X - prec I
+    HessParams p;
+    p.X = ds.d.X;
+    p.ldx = ds.d.ldx;
+    p.scale = ds.d.col_scale;
+    p.w = w;
+    p.N = N;
+    p.K = K;
+    p.nchunk = nchunk;
+    p.tiles = reinterpret_cast<const int2*>(hb.tiles);
+    p.partials = partials;
+    const dim3 grid((unsigned)(nup * nchunk));
+    switch (ds.d.dtype) {
+    case GLM_F64: hipLaunchKernelGGL(k_hess<GLM_F64>, grid, dim3(kHT), 0, s, p); break;
+    case GLM_F32: hipLaunchKernelGGL(k_hess<GLM_F32>, grid, dim3(kHT), 0, s, p); break;
+    case GLM_BF16: hipLaunchKernelGGL(k_hess<GLM_BF16>, grid, dim3(kHT), 0, s, p); break;
+    default: hipLaunchKernelGGL(k_hess<GLM_FP8_E4M3>, grid, dim3(kHT), 0, s, p); break;
+    }
+    GLM_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_hess_merge, dim3((unsigned)((int64_t)nup * kTile * kTile / kHT)), dim3(kHT), 0,
+                       s, partials, p.tiles, nchunk, K, prior->prec, H);
+    GLM_HIP_CHECK(hipGetLastError());
+    return GLM_OK;
+}
+
+}  // extern "C"

@@ -66,7 +66,8 @@ int pow2ceil(int v) {
 glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
     const int es = elem_size(d.dtype);
     const int ve = 16 / es;
-    const bool vec_ok = (d.ldx * es) % 16 == 0 && ((uintptr_t)d.X % 16) == 0;
+    // (nothing is read when N == 0)
+    const bool vec_ok = d.N == 0 || ((d.ldx * es) % 16 == 0 && ((uintptr_t)d.X % 16) == 0);
     if (!vec_ok)
         GLM_FAIL(GLM_EINVAL,
                  "plan: rows must start on 16-byte boundaries (ldx*%d a multiple of 16, X "
@@ -112,7 +113,8 @@ void scratch_need(const Plan& pl, int K, int NB, size_t* n_partials, size_t* n_g
 
 glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
                         const double* betas, const double* means, const double* precs,
-                        double prec, int nb, double* out, Scratch* s, hipStream_t stream) {
+                        double prec, int nb, double* out, Scratch* s, hipStream_t stream,
+                        double* w_out) {
     glmk::FgParams p;
     p.X = static_cast<const unsigned char*>(d.X);
     p.ldx = d.ldx;
@@ -133,7 +135,7 @@ glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* f
     p.group = pl.group;
     p.interleave = pl.interleave;
     p.family = d.family;
-    (void)NB;
+    p.w_out = NB == 1 ? w_out : nullptr;
     void* args[] = {&p};
     GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0, stream));
     return GLM_OK;

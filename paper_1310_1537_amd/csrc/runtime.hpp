@@ -92,6 +92,16 @@ struct SamplerBuf {
     size_t cap = 0;        // doubles
 };
 
+// Hessian buffers of one stream: row weights, tile partials and the tile
+// list.
+struct HessBuf {
+    double* buf = nullptr;
+    size_t cap = 0;            // doubles before the tile list
+    size_t ntick = 0;          // tile-list capacity (pairs)
+    int* tiles = nullptr;      // (tile row, tile column) pairs
+    int tiles_for = -1;        // tiles per side the list was built for
+};
+
 struct GroupSet;   // defined by the batched entry point
 
 }  // namespace glmrt
@@ -106,6 +116,7 @@ struct glm_ctx {
     std::unordered_map<int64_t, glmrt::ColSet> colsets;
     std::map<void*, glmrt::Scratch> scratch;   // keyed by stream
     std::map<void*, glmrt::SamplerBuf> sampler;  // keyed by stream
+    std::map<void*, glmrt::HessBuf> hess;        // keyed by stream
     hipStream_t own_stream = nullptr;
     // host-call staging (pinned) and device buffers
     double* h_stage = nullptr;
@@ -139,9 +150,12 @@ MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max);
 // Launches a fused kernel instance (NB slots) for nb coefficient vectors
 // (betas nb x K, means nb x K or nullptr, precs nb or nullptr -> prec) into
 // out (nb x (1 + K)); scratch must hold nblocks x NB x (1 + K) partials.
+// w_out (NB == 1 only): per-row Hessian weights are written there when not
+// nullptr.
 glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
                         const double* betas, const double* means, const double* precs,
-                        double prec, int nb, double* out, Scratch* s, hipStream_t stream);
+                        double prec, int nb, double* out, Scratch* s, hipStream_t stream,
+                        double* w_out = nullptr);
 
 // Scratch sizes a plan needs for an NB-slot instance.
 void scratch_need(const Plan& pl, int K, int NB, size_t* n_partials, size_t* n_gpart,

@@ -116,6 +116,7 @@ _SIGS = {
     "glm_diff_logpost": [_P, _I64, _P, _P, _I32, _P, _I32, ctypes.POINTER(glm_prior), _P, _P],
     "glm_diff_commit": [_P, _I64, _P, _P, _I32, _P, _P],
     "glm_mh_run": [_P, _I64, _P, _P, _P, _P, _I32, ctypes.POINTER(glm_prior), _P, _P, _P],
+    "glm_logpost_grad_hess": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P, _P],
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_probe_read_bandwidth": [_P, _P, _I64, _I32, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
@@ -300,6 +301,14 @@ def glm_diff_logpost(ctx: int, cs: int, u, beta, k: int, deltas, nd: int, prior:
 
 def glm_diff_commit(ctx: int, cs: int, u, beta, k: int, delta, stream=None) -> None:
     _check(_lib.glm_diff_commit(ctx, cs, _ptr(u), _ptr(beta), k, _ptr(delta), _stream(stream)))
+
+
+# ---------------------------------------------------------------- Hessian
+
+def glm_logpost_grad_hess(ctx: int, ds: int, beta, prior: glm_prior, out, H, stream=None) -> None:
+    """f, g (out, 1 + K) and the Hessian H (K x K) at beta; device tensors."""
+    _check(_lib.glm_logpost_grad_hess(ctx, ds, _ptr(beta), ctypes.byref(prior), _ptr(out), _ptr(H),
+                                      _stream(stream)))
 
 
 # ---------------------------------------------------------------- on-device sampler

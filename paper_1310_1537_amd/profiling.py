@@ -14,7 +14,7 @@ kernel sources, so that the benchmark reports it only while the kernel is
 unchanged.
 
     python -m paper_1310_1537_amd.profiling FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV \\
-        COPY_BYTES KERNEL_SUBSTRING OUT_JSON
+        COPY_BYTES KERNEL_SUBSTRING OUT_JSON [plain|batched|diff]
 """
 from __future__ import annotations
 
@@ -25,14 +25,19 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1310_1537_amd", "csrc", f)
-                  for f in ("fg_kernel.hpp", "glm_plain.hip")]
+_CSRC = os.path.join(ROOT, "paper_1310_1537_amd", "csrc")
+# the sources each measured kernel is built from
+KERNEL_SOURCES = {
+    "plain": ("tr_math.hpp", "fg_kernel.hpp", "glm_plain.hip"),
+    "batched": ("tr_math.hpp", "fg_kernel.hpp", "fg_batched.hpp", "glm_batched.hip"),
+    "diff": ("tr_math.hpp", "elem.hpp", "glm_diff.hip"),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kind: str = "plain") -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as fh:
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(_CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -51,7 +56,8 @@ def per_dispatch(path: str, counter: str, kernel_sub: str) -> list[float]:
 
 
 def main(argv: list[str]) -> int:
-    fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, ksub, out = argv
+    fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_bytes, ksub, out = argv[:7]
+    kind = argv[7] if len(argv) > 7 else "plain"
     copy_bytes = float(copy_bytes)
     cf = per_dispatch(cfetch_csv, "FETCH_SIZE", "copy")
     cw = per_dispatch(cwrite_csv, "WRITE_SIZE", "copy")
@@ -64,7 +70,7 @@ def main(argv: list[str]) -> int:
     k_w = copy_bytes / (sum(cw) / len(cw) * 1024.0)
     fetch = sum(f) / len(f) * 1024.0 * k_f
     write = sum(w) / len(w) * 1024.0 * k_w
-    rec = {"kernel": ksub, "kernel_source_hash": kernel_source_hash(),
+    rec = {"kernel": ksub, "sources": kind, "kernel_source_hash": kernel_source_hash(kind),
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "hbm_bytes_per_launch": fetch + write, "dispatches": [len(f), len(w)],
            "copy_scale_fetch": k_f, "copy_scale_write": k_w, "copy_bytes": copy_bytes}

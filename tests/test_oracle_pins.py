@@ -527,3 +527,61 @@ def test_poisson_rejects_nothing_the_logistic_model_rejects_for_counts():
         oracle.logpost_grad(X, y, beta, 0.1)
     f, _ = oracle.logpost_grad(X, y, beta, 0.1, family="poisson")
     assert np.isfinite(f)
+
+
+# ------------------------------------------------------------------ Hessian
+
+@pytest.mark.parametrize("family", ["logistic", "poisson"])
+def test_hessian_matches_torch_autograd(family):
+    """torch.autograd.functional.hessian of torch's own loss (BCE on logits or
+    Poisson NLL on log-rates) plus the Gaussian prior."""
+    torch = pytest.importorskip("torch")
+    if family == "logistic":
+        X, y, beta = _data(1500, 7, 40)
+    else:
+        X, y, beta = _pdata(1500, 7, 40)
+    m = np.linspace(-0.1, 0.1, 7)
+    lam = 0.8
+    H = oracle.hessian(X, beta, lam, family=family)
+    Xt = torch.from_numpy(X)
+    yt = torch.from_numpy(y.astype(np.float64))
+    mt = torch.from_numpy(m)
+
+    def f(b):
+        u = Xt @ b
+        if family == "logistic":
+            ll = -torch.nn.functional.binary_cross_entropy_with_logits(u, yt, reduction="sum")
+        else:
+            ll = -torch.nn.PoissonNLLLoss(log_input=True, full=False, reduction="sum")(u, yt)
+        d = b - mt
+        return ll - 0.5 * lam * (d * d).sum()
+
+    Ht = torch.autograd.functional.hessian(f, torch.tensor(beta)).numpy()
+    np.testing.assert_allclose(H, Ht, rtol=1e-11, atol=1e-11 * np.abs(Ht).max())
+
+
+def test_hessian_is_the_derivative_of_the_gradient():
+    X, y, beta = _data(800, 5, 41)
+    H = oracle.hessian(X, beta, 0.3)
+    h = 1e-5
+    for k in range(5):
+        e = np.zeros(5)
+        e[k] = h
+        _, gp = oracle.logpost_grad(X, y, beta + e, 0.3)
+        _, gm = oracle.logpost_grad(X, y, beta - e, 0.3)
+        np.testing.assert_allclose((gp - gm) / (2 * h), H[:, k], rtol=1e-6, atol=1e-6)
+
+
+def test_hessian_at_zero_and_its_structure():
+    """beta = 0 (logistic): every weight is 1/4 exactly, so H = -X^t X / 4 -
+    lam I, exact on integer-valued X; H is symmetric (to the rounding of
+    w x_i x_j in either order) and H + lam I is negative semi-definite."""
+    g = np.random.default_rng(42)
+    X = g.integers(-9, 10, (400, 6)).astype(np.float64)
+    H = oracle.hessian(X, np.zeros(6), 2.0)
+    want = -(X.T @ X) / 4.0 - 2.0 * np.eye(6)
+    np.testing.assert_array_equal(H, want)
+    X2, _, b2 = _data(300, 8, 43)
+    H2 = oracle.hessian(X2, b2, 0.5)
+    np.testing.assert_allclose(H2, H2.T, rtol=1e-14, atol=1e-14 * np.abs(H2).max())
+    assert np.linalg.eigvalsh(H2 + 0.5 * np.eye(8)).max() <= 1e-12
