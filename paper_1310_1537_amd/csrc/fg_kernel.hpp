@@ -56,6 +56,22 @@ template <> struct ElemSize<DT_F32> { static constexpr int v = 4; };
 template <> struct ElemSize<DT_BF16> { static constexpr int v = 2; };
 template <> struct ElemSize<DT_FP8> { static constexpr int v = 1; };
 
+// A random-walk Metropolis chain advanced by the evaluation kernel itself:
+// the launch evaluates f and g at the proposal beta_prop (its beta), and the
+// last block then takes the accept step and writes the next proposal, so a
+// chain costs one launch per step.
+struct ChainParams {
+    double* beta;             // K, the chain state
+    double* fg;               // 1 + K, f and g at the state
+    double* beta_prop;        // K, the proposal being evaluated (this launch's beta)
+    const double* incs;       // n_steps x K proposal increments
+    const double* logu;       // n_steps log-uniforms
+    unsigned* step;           // step counter t
+    int n_steps;
+    uint8_t* accepted;        // n_steps or nullptr
+    double* f_trace;          // n_steps or nullptr
+};
+
 // Kernel parameters (passed by value).  nb coefficient vectors are
 // evaluated per launch (nb <= the instance's NB; slot b's vectors at stride K,
 // its result at stride 1 + K).
@@ -80,6 +96,7 @@ struct FgParams {
     int interleave;           // 1: wave w takes batches w, w+W, ...; 0: one contiguous range
     int family;               // response family (0 logistic, 1 Poisson)
     double* w_out;            // N Hessian row weights, or nullptr (NB == 1 only)
+    const ChainParams* chain; // device copy: on-device Metropolis step, or nullptr (NB == 1)
 };
 
 // ------------------------------------------------------------ decoding
@@ -275,6 +292,37 @@ __device__ __forceinline__ double ordered_sum(const double* a, int n, int64_t st
     return s;
 }
 
+// Accept iff log U_t < f(beta_prop) - f(beta); on acceptance the state takes
+// the proposal's beta, f and g; then beta_prop = beta + incs[t + 1] and t + 1.
+// Run by all threads of the last block after fg_prop (1 + K) is written.
+template <int NT>
+__device__ __forceinline__ void chain_step(const ChainParams& c, const double* fg_prop, int K) {
+    __shared__ int s_acc;
+    __shared__ unsigned s_t;
+    if (threadIdx.x == 0) {
+        const unsigned t = *c.step;
+        s_t = t;
+        s_acc = c.logu[t] < fg_prop[0] - c.fg[0] ? 1 : 0;
+    }
+    __syncthreads();
+    const int acc = s_acc;
+    const unsigned t = s_t;
+    for (int k = threadIdx.x; k <= K; k += NT) {
+        if (acc) c.fg[k] = fg_prop[k];
+        if (k < K) {
+            const double b = acc ? c.beta_prop[k] : c.beta[k];
+            if (acc) c.beta[k] = b;
+            if ((int)t + 1 < c.n_steps) c.beta_prop[k] = b + c.incs[(int64_t)(t + 1) * K + k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (c.accepted) c.accepted[t] = (uint8_t)acc;
+        if (c.f_trace) c.f_trace[t] = acc ? fg_prop[0] : c.fg[0];
+        *c.step = t + 1;
+    }
+}
+
 // Called by every thread of every block after the block has written its
 // partial (NB x (1 + K) doubles at partials + blockIdx.x * NB * (1 + K)).
 // NT is the block size (a power of two).
@@ -345,6 +393,7 @@ __device__ __forceinline__ void merge_partials(const FgParams& p) {
         if (threadIdx.x == 0) out[0] = f_lik - 0.5 * prec * s_red[0];
         __syncthreads();
     }
+    if (p.chain) chain_step<NT>(*p.chain, p.out, p.K);
     if (threadIdx.x == 0)
         __hip_atomic_store(&p.counters[ngroups], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

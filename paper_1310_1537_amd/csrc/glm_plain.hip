@@ -114,7 +114,7 @@ void scratch_need(const Plan& pl, int K, int NB, size_t* n_partials, size_t* n_g
 glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
                         const double* betas, const double* means, const double* precs,
                         double prec, int nb, double* out, Scratch* s, hipStream_t stream,
-                        double* w_out) {
+                        double* w_out, const void* chain) {
     glmk::FgParams p;
     p.X = static_cast<const unsigned char*>(d.X);
     p.ldx = d.ldx;
@@ -136,6 +136,7 @@ glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* f
     p.interleave = pl.interleave;
     p.family = d.family;
     p.w_out = NB == 1 ? w_out : nullptr;
+    p.chain = NB == 1 ? static_cast<const glmk::ChainParams*>(chain) : nullptr;
     void* args[] = {&p};
     GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0, stream));
     return GLM_OK;

@@ -151,11 +151,13 @@ MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max);
 // (betas nb x K, means nb x K or nullptr, precs nb or nullptr -> prec) into
 // out (nb x (1 + K)); scratch must hold nblocks x NB x (1 + K) partials.
 // w_out (NB == 1 only): per-row Hessian weights are written there when not
-// nullptr.
+// nullptr.  chain (NB == 1 only): device address of a glmk::ChainParams; the
+// launch then also takes one Metropolis step (its beta is the chain's
+// proposal).
 glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
                         const double* betas, const double* means, const double* precs,
                         double prec, int nb, double* out, Scratch* s, hipStream_t stream,
-                        double* w_out = nullptr);
+                        double* w_out = nullptr, const void* chain = nullptr);
 
 // Scratch sizes a plan needs for an NB-slot instance.
 void scratch_need(const Plan& pl, int K, int NB, size_t* n_partials, size_t* n_gpart,
