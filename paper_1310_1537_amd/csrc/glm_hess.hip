@@ -31,11 +31,10 @@ namespace glmrt {
 namespace {
 
 constexpr int kTile = 128;    // output tile edge
-constexpr int kRows = 32;     // rows staged per step
 constexpr int kHT = 256;      // threads per block (4 waves)
-constexpr int kPer = kRows * 2 * kTile / kHT;   // staged elements per thread (off-diagonal tile)
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
+typedef unsigned uv4 __attribute__((ext_vector_type(4)));
 
 struct HessParams {
     const void* X;
@@ -49,16 +48,36 @@ struct HessParams {
     double* partials;         // ntiles_upper x nchunk x kTile x kTile
 };
 
+// Element e of a 16-byte chunk of stored elements, as a double.
+template <int DT>
+__device__ __forceinline__ double chunk_elem(const uv4& w, int e, float s) {
+    if constexpr (DT == GLM_F64) {
+        return __longlong_as_double((long long)(((unsigned long long)w[2 * e + 1] << 32) | w[2 * e]));
+    } else if constexpr (DT == GLM_F32) {
+        return (double)__uint_as_float(w[e]);
+    } else if constexpr (DT == GLM_BF16) {
+        return (double)__uint_as_float(((w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) << 16);
+    } else {
+        const unsigned byte = (w[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+        return glmk::Elem<GLM_FP8_E4M3>::value((unsigned char)byte, s);
+    }
+}
+
 // Block (tile, chunk): sum over the chunk's rows of w_n x_n,i x_n,j for the
 // tile's 128 x 128 entries; each wave owns a 64 x 64 quadrant (4 x 4 MFMA
-// blocks of 16 x 16).  Rows are staged kRows at a time; the next rows'
-// elements are loaded into registers while the matrix cores work on the
-// current ones.  Every thread stages one fixed column (thread t takes column
-// t mod width, rows t / width + q * 256 / width).
+// blocks of 16 x 16).  Rows are staged R = 32 at a time with 16-byte loads; the next R rows are loaded into registers while the
+// matrix cores work on the current ones.  Thread t stages the fixed 16-byte
+// column chunk t mod CW of rows t / CW + q * 256 / CW (CW chunks per staged
+// row).  A chunk starting at or past column K is not read; the part of a
+// chunk past K (row padding up to ldx) is zeroed.
 template <int DT>
 __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
-    using E = glmk::Elem<DT>;
-    const typename E::T* X = static_cast<const typename E::T*>(p.X);
+    constexpr int ES = DT == GLM_F64 ? 8 : DT == GLM_F32 ? 4 : DT == GLM_BF16 ? 2 : 1;
+    constexpr int VE = 16 / ES;                 // elements per chunk
+    constexpr int R = 32;                       // rows per step
+    constexpr int CR = kTile / VE;              // chunks per column range
+    constexpr int NPMAX = R * 2 * CR / kHT;     // chunks per thread (off-diagonal tile)
+    const unsigned char* X = static_cast<const unsigned char*>(p.X);
     const int tile = blockIdx.x / p.nchunk;
     const int chunk = blockIdx.x % p.nchunk;
     const int2 tc = p.tiles[tile];
@@ -68,37 +87,34 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
     const int64_t r1 = p.N * (chunk + 1) / p.nchunk;
 
     // xs[r][c]: c < kTile the i-range, c >= kTile the j-range (off-diagonal tiles)
-    __shared__ double xs[kRows][2 * kTile + 1];
-    __shared__ double ws[kRows];
+    __shared__ double xs[R][2 * kTile + 1];
+    __shared__ double ws[R];
 
-    const int width = diag ? kTile : 2 * kTile;       // staged columns
-    const int nper = kRows * width / kHT;              // staged elements per thread
-    const int sc = threadIdx.x % width;                // this thread's staged column
-    const int srow = threadIdx.x / width;              // first staged row
-    const int rstep = kHT / width;
-    const int col = sc < kTile ? i0 + sc : j0 + (sc - kTile);
-    const bool col_ok = col < p.K;
-    const float cs = (DT == GLM_FP8_E4M3 && col_ok) ? p.scale[col] : 1.0f;
+    const int cw = diag ? CR : 2 * CR;                 // staged chunks per row
+    const int nper = R * cw / kHT;                     // chunks per thread
+    const int cc = threadIdx.x % cw;                   // this thread's chunk column
+    const int srow = threadIdx.x / cw;                 // first staged row
+    const int rstep = kHT / cw;
+    const int col0 = cc < CR ? i0 + cc * VE : j0 + (cc - CR) * VE;   // first column of the chunk
+    const bool chunk_ok = col0 < p.K;
+    const int lcol = cc * VE;                          // LDS column of the chunk
+    float cs[VE];
+#pragma unroll
+    for (int e = 0; e < VE; ++e)
+        cs[e] = (DT == GLM_FP8_E4M3 && col0 + e < p.K) ? p.scale[col0 + e] : 1.0f;
 
-    // Loads are issued unconditionally from clamped (always valid) addresses
-    // and masked afterwards, so that they are all in flight at once.
-    const int colc = col_ok ? col : p.K - 1;
-    double v[kPer];
-    double wv = 0.0;
+    // loads from clamped (always valid) addresses, masked afterwards, so that
+    // they are all in flight at once
+    uv4 raw[NPMAX];
+    double wl = 0.0;
     auto fetch = [&](int64_t r) {
-        typename E::T raw[kPer];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < NPMAX; ++q) {
             const int64_t row = min(r + srow + q * rstep, r1 - 1);
-            raw[q] = X[row * p.ldx + colc];
+            const uv4* src = reinterpret_cast<const uv4*>(X + (row * p.ldx + (chunk_ok ? col0 : 0)) * ES);
+            raw[q] = (q < nper) ? *src : uv4{0u, 0u, 0u, 0u};
         }
-        const double wl = p.w[min(r + (int64_t)(threadIdx.x % kRows), r1 - 1)];
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int64_t row = r + srow + q * rstep;
-            v[q] = (col_ok && row < r1 && q < nper) ? E::value(raw[q], cs) : 0.0;
-        }
-        wv = r + (int64_t)(threadIdx.x % kRows) < r1 ? wl : 0.0;
+        wl = p.w[min(r + (int64_t)(threadIdx.x % R), r1 - 1)];
     };
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -111,18 +127,22 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
         for (int b = 0; b < 4; ++b) acc[a][b] = dv4{0.0, 0.0, 0.0, 0.0};
 
     if (r0 < r1) fetch(r0);
-    for (int64_t r = r0; r < r1; r += kRows) {
+    for (int64_t r = r0; r < r1; r += R) {
         __syncthreads();   // the previous step's MFMA reads of xs are done
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < NPMAX; ++q) {
             if (q >= nper) break;
-            xs[srow + q * rstep][sc] = v[q];
-        }
-        if (threadIdx.x < kRows) ws[threadIdx.x] = wv;
-        __syncthreads();
-        if (r + kRows < r1) fetch(r + kRows);
+            const int rr = srow + q * rstep;
+            const bool row_ok = r + rr < r1 && chunk_ok;
 #pragma unroll
-        for (int k0 = 0; k0 < kRows; k0 += 4) {
+            for (int e = 0; e < VE; ++e)
+                xs[rr][lcol + e] = (row_ok && col0 + e < p.K) ? chunk_elem<DT>(raw[q], e, cs[e]) : 0.0;
+        }
+        if (threadIdx.x < R) ws[threadIdx.x] = r + threadIdx.x < r1 ? wl : 0.0;
+        __syncthreads();
+        if (r + R < r1) fetch(r + R);
+#pragma unroll
+        for (int k0 = 0; k0 < R; k0 += 4) {
             // A[i][k] = w_k x_k,(i0+i), B[k][j] = x_k,(j0+j); lane: i or j = lane % 16, k = lane / 16
             const int kk = k0 + (lane >> 4);
             const double wk = ws[kk];
@@ -209,7 +229,7 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
     const int ntile = (K + kTile - 1) / kTile;
     const int nup = ntile * (ntile + 1) / 2;
     const int nchunk = (int)std::max<int64_t>(
-        1, std::min<int64_t>((2 * (int64_t)ctx->num_cu + nup - 1) / nup, (N + kRows - 1) / kRows));
+        1, std::min<int64_t>((2 * (int64_t)ctx->num_cu + nup - 1) / nup, (N + 31) / 32));
 
     // per-stream buffers: w (N), partials, tile list
     HessBuf& hb = ctx->hess[stream];
