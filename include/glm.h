@@ -457,6 +457,14 @@ glm_status glm_probe_roundtrip(glm_ctx* ctx, int32_t K, int32_t iters, double* u
 glm_status glm_probe_read_bandwidth(glm_ctx* ctx, const void* buf, int64_t bytes,
                                     int32_t blocks_per_cu, int32_t iters, double* gbps);
 
+/* The measured ceiling that the Hessian's matrix-core rate is compared with:
+ * 2 blocks per compute unit of 4 waves, each wave issuing `iters` rounds of
+ * 16 independent FP64 16x16x4 matrix instructions (no memory traffic), timed
+ * with events on the context's stream after one short untimed launch.  Writes
+ * the achieved TFLOP/s to *tflops.  Blocks until done.  Errors: GLM_EINVAL
+ * (NULL, iters < 1), GLM_ENOMEM, GLM_EHIP. */
+glm_status glm_probe_mfma_f64(glm_ctx* ctx, int32_t iters, double* tflops);
+
 /* ----------------------------------------------------- storage conversions */
 
 /* BF16 copy of an FP32 matrix, round to nearest even (NaN stays NaN).

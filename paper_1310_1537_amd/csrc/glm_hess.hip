@@ -202,6 +202,24 @@ __global__ __launch_bounds__(kHT) void k_hess_merge(const double* __restrict__ p
     if (gi != gj) H[(int64_t)gj * K + gi] = h;
 }
 
+// Matrix-core throughput probe: 16 independent FP64 16x16x4 accumulators per
+// wave, `iters` rounds; the sum of the results is written (per lane) only so
+// that the work is kept.
+__global__ __launch_bounds__(kHT) void k_mfma_probe(double* __restrict__ sink, int iters, double seed) {
+    dv4 acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = dv4{0.0, 0.0, 0.0, 0.0};
+    const double a = seed + threadIdx.x, b = seed - threadIdx.x;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+    sink[(int64_t)blockIdx.x * kHT + threadIdx.x] = s;
+}
+
 }  // namespace
 }  // namespace glmrt
 
@@ -296,6 +314,43 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
     hipLaunchKernelGGL(k_hess_merge, dim3((unsigned)((int64_t)nup * kTile * kTile / kHT)), dim3(kHT), 0,
                        s, partials, p.tiles, nchunk, K, prior->prec, H);
     GLM_HIP_CHECK(hipGetLastError());
+    return GLM_OK;
+}
+
+glm_status glm_probe_mfma_f64(glm_ctx* ctx, int32_t iters, double* tflops) {
+    clear_error();
+    if (!ctx || !tflops || iters < 1) GLM_FAIL(GLM_EINVAL, "glm_probe_mfma_f64: bad argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    const int blocks = 2 * ctx->num_cu;
+    double* sink = nullptr;
+    if (hipMalloc((void**)&sink, (size_t)blocks * kHT * sizeof(double)) != hipSuccess)
+        GLM_FAIL(GLM_ENOMEM, "glm_probe_mfma_f64: device allocation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    hipStream_t s = ctx->own_stream;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mfma_probe, dim3(blocks), dim3(kHT), 0, s, sink, 8, 1.0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mfma_probe, dim3(blocks), dim3(kHT), 0, s, sink, iters, 1.0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    if (e != hipSuccess) GLM_FAIL(GLM_EHIP, "glm_probe_mfma_f64: %s", hipGetErrorString(e));
+    // flops: waves x rounds x 16 instructions x (16 x 16 x 4 multiply-adds x 2)
+    const double flops = (double)blocks * (kHT / 64) * iters * 16.0 * 2048.0;
+    *tflops = flops / (ms * 1e-3) / 1e12;
     return GLM_OK;
 }
 

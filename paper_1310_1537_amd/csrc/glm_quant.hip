@@ -92,6 +92,107 @@ __global__ void k_quant_fp8(const float* X, int64_t N, int K, int64_t ldx, const
     }
 }
 
+// Row-wise forms for rows of whole 4-float chunks (K, ldx and ldq multiples
+// of 4, 16-byte aligned X): one 16-byte load and one 8- or 4-byte store per
+// four elements; the threads of a block take the chunks of a row, the blocks
+// take rows in turn.
+typedef float qfv4 __attribute__((ext_vector_type(4)));
+typedef unsigned quv2 __attribute__((ext_vector_type(2)));
+
+// Four rows per trip with their loads issued together.
+constexpr int kRowUnroll = 4;
+
+__global__ __launch_bounds__(256) void k_quant_bf16_v4(const float* X, int64_t N, int K, int64_t ldx,
+                                                       uint16_t* Q, int64_t ldq) {
+    const int kc = K >> 2;
+    const int64_t G = gridDim.x;
+    for (int c = threadIdx.x; c < kc; c += blockDim.x) {
+        for (int64_t n0 = blockIdx.x; n0 < N; n0 += kRowUnroll * G) {
+            qfv4 v[kRowUnroll];
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                const int64_t n = min(n0 + u * G, N - 1);
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const qfv4*>(X + n * ldx) + c);
+            }
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                const int64_t n = n0 + u * G;
+                if (n >= N) break;
+                quv2 o;
+                o.x = (unsigned)bf16_rne(v[u].x) | ((unsigned)bf16_rne(v[u].y) << 16);
+                o.y = (unsigned)bf16_rne(v[u].z) | ((unsigned)bf16_rne(v[u].w) << 16);
+                reinterpret_cast<quv2*>(Q + n * ldq)[c] = o;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_col_absmax_v4(const float* X, int64_t N, int K, int64_t ldx,
+                                                       unsigned* amax) {
+    const int kc = K >> 2;
+    const int64_t G = gridDim.x;
+    for (int c = threadIdx.x; c < kc; c += blockDim.x) {
+        unsigned m0 = 0u, m1 = 0u, m2 = 0u, m3 = 0u;
+        for (int64_t n0 = blockIdx.x; n0 < N; n0 += kRowUnroll * G) {
+            qfv4 v[kRowUnroll];
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                const int64_t n = min(n0 + u * G, N - 1);   // a repeated row changes no maximum
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const qfv4*>(X + n * ldx) + c);
+            }
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                m0 = max(m0, __float_as_uint(fabsf(v[u].x)));
+                m1 = max(m1, __float_as_uint(fabsf(v[u].y)));
+                m2 = max(m2, __float_as_uint(fabsf(v[u].z)));
+                m3 = max(m3, __float_as_uint(fabsf(v[u].w)));
+            }
+        }
+        if (m0) atomicMax(&amax[4 * c], m0);
+        if (m1) atomicMax(&amax[4 * c + 1], m1);
+        if (m2) atomicMax(&amax[4 * c + 2], m2);
+        if (m3) atomicMax(&amax[4 * c + 3], m3);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_quant_fp8_v4(const float* X, int64_t N, int K, int64_t ldx,
+                                                      const float* scale, uint8_t* Q, int64_t ldq) {
+    const int kc = K >> 2;
+    const int64_t G = gridDim.x;
+    for (int c = threadIdx.x; c < kc; c += blockDim.x) {
+        const qfv4 s = reinterpret_cast<const qfv4*>(scale)[c];
+        for (int64_t n0 = blockIdx.x; n0 < N; n0 += kRowUnroll * G) {
+            qfv4 v[kRowUnroll];
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                const int64_t n = min(n0 + u * G, N - 1);
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const qfv4*>(X + n * ldx) + c);
+            }
+#pragma unroll
+            for (int u = 0; u < kRowUnroll; ++u) {
+                const int64_t n = n0 + u * G;
+                if (n >= N) break;
+                const unsigned o = (unsigned)e4m3_rne_sat(__fdiv_rn(v[u].x, s.x)) |
+                                   ((unsigned)e4m3_rne_sat(__fdiv_rn(v[u].y, s.y)) << 8) |
+                                   ((unsigned)e4m3_rne_sat(__fdiv_rn(v[u].z, s.z)) << 16) |
+                                   ((unsigned)e4m3_rne_sat(__fdiv_rn(v[u].w, s.w)) << 24);
+                reinterpret_cast<unsigned*>(Q + n * ldq)[c] = o;
+            }
+        }
+    }
+}
+
+bool rows_of_chunks(const void* X, int K, int64_t ldx, const void* Q, int64_t ldq, int qalign) {
+    return K % 4 == 0 && ldx % 4 == 0 && ldq % 4 == 0 && (uintptr_t)X % 16 == 0 &&
+           (Q == nullptr || (uintptr_t)Q % qalign == 0);
+}
+
+dim3 row_block(int K) { return dim3((unsigned)std::min(256, std::max(64, ((K / 4 + 63) / 64) * 64))); }
+
+unsigned row_grid(const glm_ctx* ctx, int64_t N) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(N, (int64_t)ctx->num_cu * 16));
+}
+
 glm_status check_conv(glm_ctx* ctx, const void* X, int64_t N, int32_t K, int64_t ldx,
                       const void* Q, int64_t ldq, const char* who) {
     if (!ctx) GLM_FAIL(GLM_EINVAL, "%s: ctx is NULL", who);
@@ -119,8 +220,12 @@ glm_status glm_quantize_bf16(glm_ctx* ctx, const float* X, int64_t N, int32_t K,
     clear_error();
     glm_status st = check_conv(ctx, X, N, K, ldx, Q, ldq, "glm_quantize_bf16");
     if (st != GLM_OK || N == 0) return st;
-    hipLaunchKernelGGL(k_quant_bf16, dim3(grid_for(N * K)), dim3(256), 0, (hipStream_t)stream, X,
-                       N, K, ldx, Q, ldq);
+    if (rows_of_chunks(X, K, ldx, Q, ldq, 8))
+        hipLaunchKernelGGL(k_quant_bf16_v4, dim3(row_grid(ctx, N)), row_block(K), 0,
+                           (hipStream_t)stream, X, N, K, ldx, Q, ldq);
+    else
+        hipLaunchKernelGGL(k_quant_bf16, dim3(grid_for(N * K)), dim3(256), 0, (hipStream_t)stream, X,
+                           N, K, ldx, Q, ldq);
     GLM_HIP_CHECK(hipGetLastError());
     return GLM_OK;
 }
@@ -135,7 +240,10 @@ glm_status glm_fp8_col_scales(glm_ctx* ctx, const float* X, int64_t N, int32_t K
     // the max is accumulated in the scale buffer itself (as bits), then converted
     unsigned* amax = reinterpret_cast<unsigned*>(scale);
     hipLaunchKernelGGL(k_zero_u32, dim3((K + 255) / 256), dim3(256), 0, s, amax, K);
-    if (N > 0) {
+    if (N > 0 && rows_of_chunks(X, K, ldx, nullptr, 4, 1)) {
+        const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(N, (int64_t)ctx->num_cu * 4));
+        hipLaunchKernelGGL(k_col_absmax_v4, dim3(nb), row_block(K), 0, s, X, N, K, ldx, amax);
+    } else if (N > 0) {
         const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (N + 1023) / 1024));
         hipLaunchKernelGGL(k_col_absmax, dim3(nb), dim3(std::min(256, ((K + 63) / 64) * 64)), 0, s, X,
                            N, K, ldx, amax);
@@ -151,8 +259,12 @@ glm_status glm_quantize_fp8(glm_ctx* ctx, const float* X, int64_t N, int32_t K, 
     glm_status st = check_conv(ctx, X, N, K, ldx, Q, ldq, "glm_quantize_fp8");
     if (st != GLM_OK || N == 0) return st;
     if (!scale) GLM_FAIL(GLM_EINVAL, "glm_quantize_fp8: scale is NULL");
-    hipLaunchKernelGGL(k_quant_fp8, dim3(grid_for(N * K)), dim3(256), 0, (hipStream_t)stream, X, N,
-                       K, ldx, scale, Q, ldq);
+    if (rows_of_chunks(X, K, ldx, Q, ldq, 4) && (uintptr_t)scale % 16 == 0)
+        hipLaunchKernelGGL(k_quant_fp8_v4, dim3(row_grid(ctx, N)), row_block(K), 0,
+                           (hipStream_t)stream, X, N, K, ldx, scale, Q, ldq);
+    else
+        hipLaunchKernelGGL(k_quant_fp8, dim3(grid_for(N * K)), dim3(256), 0, (hipStream_t)stream, X,
+                           N, K, ldx, scale, Q, ldq);
     GLM_HIP_CHECK(hipGetLastError());
     return GLM_OK;
 }

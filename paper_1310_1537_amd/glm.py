@@ -119,6 +119,7 @@ _SIGS = {
     "glm_logpost_grad_hess": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P, _P],
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_probe_read_bandwidth": [_P, _P, _I64, _I32, _I32, ctypes.POINTER(_D)],
+    "glm_probe_mfma_f64": [_P, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
     "glm_fp8_col_scales": [_P, _P, _I64, _I32, _I64, _P, _P],
     "glm_quantize_fp8": [_P, _P, _I64, _I32, _I64, _P, _P, _I64, _P],
@@ -465,6 +466,13 @@ def glm_probe_read_bandwidth(ctx: int, buf, nbytes: int | None = None, blocks_pe
     _check(_lib.glm_probe_read_bandwidth(ctx, _ptr(buf), int(nbytes), blocks_per_cu, iters,
                                          ctypes.byref(gb)))
     return gb.value
+
+
+def glm_probe_mfma_f64(ctx: int, iters: int = 2000) -> float:
+    """TFLOP/s of back-to-back FP64 16x16x4 matrix instructions."""
+    tf = ctypes.c_double()
+    _check(_lib.glm_probe_mfma_f64(ctx, iters, ctypes.byref(tf)))
+    return tf.value
 
 
 def glm_quantize_bf16(ctx: int, X, Q, stream=None) -> None:

@@ -134,3 +134,11 @@ def test_repeated_calls_bitwise_and_mid_size(ctx):
                             range(32)))
     Ho = np.sum(parts, axis=0) - w.prec * np.eye(256)
     _check(H1, Ho, _bound(w.X.astype(np.float64), b) + 64 * 2.0 ** -53 * np.abs(Ho))
+
+
+def test_mfma_probe(ctx):
+    tf = glm.glm_probe_mfma_f64(ctx, 200)
+    assert 1.0 < tf < 200.0
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_probe_mfma_f64(ctx, 0)
+    assert e.value.status == glm.GLM_EINVAL
