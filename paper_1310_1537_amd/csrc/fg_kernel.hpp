@@ -31,7 +31,8 @@
 // notes the resulting two-stage reduction, Sec. 4.5).  Here it stays in one
 // launch: blocks are grouped by GROUP; the last block of a group to finish
 // (atomic ticket) adds the group's partials in block order, and the last
-// group to finish adds the group sums in group order and the prior.  No
+// group to finish adds the group sums in group order and the prior (a single
+// group goes straight on to the final sums).  No
 // floating-point atomics are used, so the result is bitwise reproducible.
 #pragma once
 
@@ -356,15 +357,18 @@ __device__ __forceinline__ void merge_partials(const FgParams& p) {
         __hip_atomic_store(&p.counters[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = __hip_atomic_fetch_add(&p.counters[ngroups], 1u, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == (unsigned)(ngroups - 1)) ? 1u : 0u;
-        if (s_last) __threadfence();
+    if (ngroups > 1) {
+        // second level: the last group to finish adds the group sums
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const unsigned prev = __hip_atomic_fetch_add(&p.counters[ngroups], 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            s_last = (prev == (unsigned)(ngroups - 1)) ? 1u : 0u;
+            if (s_last) __threadfence();
+        }
+        __syncthreads();
+        if (!s_last) return;
     }
-    __syncthreads();
-    if (!s_last) return;
 
     // Final sums in group order, plus each slot's Gaussian prior N(m, prec^-1 I).
     for (int b = 0; b < p.nb; ++b) {

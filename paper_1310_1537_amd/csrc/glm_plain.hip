@@ -97,7 +97,8 @@ glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
     p.nblocks = (int)std::max<int64_t>(1, std::min(need, target));
     p.interleave = 1;
     if (const char* e = std::getenv("GLM_INTERLEAVE")) p.interleave = std::atoi(e) != 0;
-    p.group = std::max(1, (int)std::ceil(std::sqrt((double)p.nblocks)));
+    // one merge level for small grids, two (groups of about sqrt(nblocks)) above
+    p.group = p.nblocks <= 64 ? p.nblocks : std::max(1, (int)std::ceil(std::sqrt((double)p.nblocks)));
     *plan = p;
     return GLM_OK;
 }
