@@ -288,29 +288,27 @@ bool dispatch(glm_server* s) {
     bool has_mean = false;
     for (const Request& r : batch) has_mean |= r.has_mean;
     if (ok) {
+        // one host-to-device copy per pass: betas (nb x K), precisions (nb),
+        // then the means (nb x K) when any request has one
         double* hb = sl->h_in;
-        double* hm = hb + (size_t)NB * K;
-        double* hp = hm + (size_t)NB * K;
+        double* hp = hb + (size_t)nb * K;
+        double* hm = hp + nb;
         for (int i = 0; i < nb; ++i) {
             std::memcpy(hb + (size_t)i * K, batch[i].beta.data(), K * 8);
-            if (batch[i].has_mean)
-                std::memcpy(hm + (size_t)i * K, batch[i].mean.data(), K * 8);
-            else
-                std::fill(hm + (size_t)i * K, hm + (size_t)(i + 1) * K, 0.0);
             hp[i] = batch[i].prec;
+            if (has_mean) {
+                if (batch[i].has_mean)
+                    std::memcpy(hm + (size_t)i * K, batch[i].mean.data(), K * 8);
+                else
+                    std::fill(hm + (size_t)i * K, hm + (size_t)(i + 1) * K, 0.0);
+            }
         }
-        // copy only what the pass reads: betas, then means (if any) and precs
-        ok = hipMemcpyAsync(sl->d_in, hb, (size_t)nb * K * 8, hipMemcpyHostToDevice, sl->stream) == hipSuccess;
-        if (ok && has_mean)
-            ok = hipMemcpyAsync(sl->d_in + (size_t)NB * K, hm, (size_t)nb * K * 8, hipMemcpyHostToDevice,
-                                sl->stream) == hipSuccess;
-        if (ok)
-            ok = hipMemcpyAsync(sl->d_in + (size_t)2 * NB * K, hp, (size_t)nb * 8, hipMemcpyHostToDevice,
-                                sl->stream) == hipSuccess;
+        const size_t words = (size_t)nb * K + nb + (has_mean ? (size_t)nb * K : 0);
+        ok = hipMemcpyAsync(sl->d_in, hb, words * 8, hipMemcpyHostToDevice, sl->stream) == hipSuccess;
         if (ok)
             ok = launch_fused(ds.dev, ds.plan, fn, NB, sl->d_in,
-                              has_mean ? sl->d_in + (size_t)NB * K : nullptr,
-                              sl->d_in + (size_t)2 * NB * K, 0.0, nb, sl->d_out, &sl->scratch,
+                              has_mean ? sl->d_in + (size_t)nb * K + nb : nullptr,
+                              sl->d_in + (size_t)nb * K, 0.0, nb, sl->d_out, &sl->scratch,
                               sl->stream) == GLM_OK;
         if (ok)
             ok = hipMemcpyAsync(sl->h_out, sl->d_out, (size_t)nb * (K + 1) * 8, hipMemcpyDeviceToHost,
