@@ -899,7 +899,7 @@ def main() -> int:
                     help="also run one request per pass at the first two rates")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the row-sharded design is described, not built). Run with --gpus 1.",
               file=sys.stderr)
         return 2

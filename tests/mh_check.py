@@ -6,7 +6,7 @@ TEST INFRASTRUCTURE: imports the oracle.  Used by tests/test_gpu_mh.py and
 runnable on its own for the full-size storage-precision workload:
 
     python tests/mh_check.py --n 8000000 --k 512 --steps 20000 --audit 0.0025 \
-        --out gpurun_out/mh_full.json
+        --out mh_full.json
 
 The sampler (Sec. 2.2 describes the MH step inside Gibbs; Sec. 3.1.1 gives the
 logistic model) proposes beta' = beta + e, e ~ N(0, s^2 I), and accepts iff
