@@ -176,7 +176,10 @@ bool ensure_slot_capacity(Slot& sl, int NB, int K, const Plan& pl) {
         sl.d_out = nullptr;
         sl.cap_in = sl.cap_out = 0;
         if (hipHostMalloc((void**)&sl.h_in, need_in * 8) != hipSuccess) return false;
-        if (hipHostMalloc((void**)&sl.h_out, need_out * 8) != hipSuccess) return false;
+        // results are written by the kernel straight into coherent pinned host
+        // memory (no device-to-host copy per pass)
+        if (hipHostMalloc((void**)&sl.h_out, need_out * 8, hipHostMallocCoherent) != hipSuccess)
+            return false;
         if (hipMalloc((void**)&sl.d_in, (need_in + need_out) * 8) != hipSuccess) return false;
         sl.d_out = sl.d_in + need_in;
         sl.cap_in = need_in;
@@ -308,11 +311,8 @@ bool dispatch(glm_server* s) {
         if (ok)
             ok = launch_fused(ds.dev, ds.plan, fn, NB, sl->d_in,
                               has_mean ? sl->d_in + (size_t)nb * K + nb : nullptr,
-                              sl->d_in + (size_t)nb * K, 0.0, nb, sl->d_out, &sl->scratch,
+                              sl->d_in + (size_t)nb * K, 0.0, nb, sl->h_out, &sl->scratch,
                               sl->stream) == GLM_OK;
-        if (ok)
-            ok = hipMemcpyAsync(sl->h_out, sl->d_out, (size_t)nb * (K + 1) * 8, hipMemcpyDeviceToHost,
-                                sl->stream) == hipSuccess;
         if (ok) ok = hipEventRecord(sl->done, sl->stream) == hipSuccess;
     }
     std::lock_guard<std::mutex> lk(s->mu);
