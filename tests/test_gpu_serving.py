@@ -254,3 +254,39 @@ def test_multi_ragged_k(ctx, K):
     for b in range(6):
         _check(o[b, 0], o[b, 1:], X.astype(np.float64), y, B[b], 0.01)
     glm.glm_dataset_unregister(ctx, ds)
+
+
+@pytest.mark.timeout(900)
+def test_serving_workload_full_configuration(ctx):
+    """The 64 data sets of the serving workload (N log-uniform on [1e3, 2e6],
+    K in {8, 32, 128, 512}, BF16 or FP32 storage), device-resident in one
+    server, two requests per data set submitted together; every result is
+    checked against the oracle on the stored values within the derived
+    bound."""
+    import synth
+    spec = synth.serving_specs(64)
+    srv = _server(ctx)
+    rng = np.random.default_rng(90)
+    keep, reqs = [], []
+    for i in range(64):
+        X, y, bt = synth.serving_dataset(i, spec)
+        if spec.dtype[i] == "bf16":
+            S, dt = oracle.quantize_bf16(X), glm.GLM_BF16
+        else:
+            S, dt = X, glm.GLM_F32
+        Xd, yd = to_dev(S), to_dev(y)
+        keep.append((Xd, yd))
+        ds = glm.glm_server_add_dataset(srv, glm.make_desc(Xd, yd, dtype=dt), on_device=True)
+        for _ in range(2):
+            beta = bt + 0.01 * rng.standard_normal(len(bt))
+            reqs.append((i, S, y, dt, beta, glm.glm_server_submit(srv, ds, beta, 0.01)))
+    for i, S, y, dt, beta, t in reqs:
+        g = np.empty(len(beta))
+        f = glm.glm_server_wait(srv, t, g)
+        if dt == glm.GLM_BF16:
+            _check(f, g, oracle.decode_bf16(S), y, beta, 0.01, Xo=S, okw={"dtype": "bf16"})
+        else:
+            _check(f, g, S.astype(np.float64), y, beta, 0.01)
+    st = glm.glm_server_stats(srv)
+    assert st["completed"] == 128 and st["failed"] == 0
+    glm.glm_server_destroy(srv)
