@@ -538,7 +538,8 @@ def bench_serving(args):
     ptr_table = np.array([[b[j].ctypes.data for j in range(pool)] for b in betas], np.uint64)
 
     def run(nbmax, rate, n_req, seed):
-        srv = glm.glm_server_create(ctx, 200 * (1 << 30), nbmax, 4, 8, 1 << 22)
+        srv = glm.glm_server_create(ctx, 200 * (1 << 30), nbmax, args.serving_streams,
+                                    args.serving_slots, 1 << 22, args.serving_max_sets)
         ids = [glm.glm_server_add_dataset(srv, glm.make_desc(X, y, dtype=dt), on_device=True)
                for X, y, dt in keep]
         # warm: one pass per data set
@@ -568,6 +569,8 @@ def bench_serving(args):
                 "latency_p50_us": st["latency_p50_us"], "latency_p99_us": st["latency_p99_us"],
                 "latency_mean_us": st["latency_mean_us"], "passes": st["passes"],
                 "mean_pass_width": st["betas_in_passes"] / max(1, st["passes"]),
+                "launches": st["launches"],
+                "mean_sets_per_launch": st["passes"] / max(1, st["launches"]),
                 "pass_width_hist": st["pass_width_hist"][1:], "failed": st["failed"]}
 
     rates = [int(r) for r in args.serving_rates.split(",")]
@@ -577,7 +580,8 @@ def bench_serving(args):
         res_b.append(run(8, r, n_req, k))
         print(f"[bench] batched  rate {r}: {res_b[-1]['throughput']:.0f} req/s "
               f"p50 {res_b[-1]['latency_p50_us']:.0f} us p99 {res_b[-1]['latency_p99_us']:.0f} us "
-              f"width {res_b[-1]['mean_pass_width']:.2f}", file=sys.stderr, flush=True)
+              f"width {res_b[-1]['mean_pass_width']:.2f} "
+              f"sets/launch {res_b[-1]['mean_sets_per_launch']:.2f}", file=sys.stderr, flush=True)
     for k, r in enumerate(rates[:2] if args.serving_baseline else []):
         n_req = int(min(r * args.serving_seconds, 100_000))
         res_1.append(run(1, r, n_req, 10 + k))
@@ -595,7 +599,8 @@ def bench_serving(args):
         "config": {"workload": f"serving: {nd} device-resident data sets ({total_bytes / 1e9:.2f} GB, "
                                "N log-uniform 1e3..2e6, K in {8,32,128,512}, BF16/FP32 50/50), "
                                "512 chains, open-loop Poisson arrivals",
-                   "hbm_budget_GB": 200, "max_beta_per_pass": 8, "slots": 8, "streams": 4},
+                   "hbm_budget_GB": 200, "max_beta_per_pass": 8, "slots": args.serving_slots,
+                   "streams": args.serving_streams, "max_sets_per_launch": args.serving_max_sets or 32},
         "latency_us": {"p50": top["latency_p50_us"], "p99": top["latency_p99_us"]},
         "by_rate": res_b, "one_request_per_pass": res_1,
     }
@@ -895,6 +900,10 @@ def main() -> int:
     ap.add_argument("--latency-calls", type=int, default=200)
     ap.add_argument("--serving-seconds", type=float, default=1.0)
     ap.add_argument("--serving-rates", default="20000,50000,100000,200000")
+    ap.add_argument("--serving-slots", type=int, default=8, help="passes in flight")
+    ap.add_argument("--serving-streams", type=int, default=4)
+    ap.add_argument("--serving-max-sets", type=int, default=0,
+                    help="data sets per launch at most (0: the server default)")
     ap.add_argument("--serving-baseline", type=int, default=1,
                     help="also run one request per pass at the first two rates")
     args = ap.parse_args()

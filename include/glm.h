@@ -250,10 +250,14 @@ glm_status glm_logpost_grad_batched(glm_ctx* ctx, glm_groupset* gs, const double
  * requests (one beta each) for registered data sets and collect results by
  * ticket.  A scheduler thread packs queued requests of one data set into a
  * single pass over X that evaluates up to max_beta_per_pass coefficient
- * vectors (glm_logpost_grad_multi's kernels), and keeps up to n_slots passes
- * in flight on n_streams streams: requests arriving while passes run join the
- * next free slot (continuous batching).  A request's result does not depend
- * on which other requests share its pass (bitwise).
+ * vectors (glm_logpost_grad_multi's kernels), and keeps up to n_slots
+ * launches in flight on n_streams streams: requests arriving while passes run
+ * join the next free slot (continuous batching).  The passes of up to
+ * max_sets_per_pass data sets that share a kernel geometry (storage type and
+ * row width) and have requests queued go into one launch (a fleet launch):
+ * small data sets are latency-bound, and one launch then pays that latency
+ * for all of them.  A request's result does not depend on which other
+ * requests share its pass or its launch (bitwise).
  *
  * Data sets given with host pointers are copied to device memory on first
  * use (admission) if they fit hbm_budget_bytes together with the resident
@@ -266,13 +270,15 @@ typedef struct {
     uint64_t hbm_budget_bytes;   /* device bytes the server may hold for data sets */
     int32_t max_beta_per_pass;   /* 1..8: coefficient vectors per pass over X       */
     int32_t n_streams;           /* device streams passes rotate over              */
-    int32_t n_slots;             /* passes in flight at most                       */
+    int32_t n_slots;             /* launches in flight at most                     */
     int32_t queue_capacity;      /* queued requests at most (submit: GLM_EAGAIN)    */
+    int32_t max_sets_per_pass;   /* data sets per launch at most: 1 = one per
+                                    launch; 0 = the default, 32; at most 256        */
 } glm_server_config;
 
 typedef struct {
     uint64_t submitted, completed, cancelled, failed;
-    uint64_t passes;             /* passes launched                                 */
+    uint64_t passes;             /* passes launched (one data set each)             */
     uint64_t betas_in_passes;    /* requests served by them                         */
     uint64_t admissions, evictions;
     uint64_t resident_bytes;
@@ -282,6 +288,7 @@ typedef struct {
     double latency_p50_us;       /* submit -> result ready, finished requests       */
     double latency_p99_us;
     double latency_mean_us;
+    uint64_t launches;           /* kernel launches that carried the passes         */
 } glm_server_metrics;
 
 /* Starts the scheduler thread.  Errors: GLM_EINVAL, GLM_EHIP. */

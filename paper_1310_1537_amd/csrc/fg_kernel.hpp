@@ -325,15 +325,16 @@ __device__ __forceinline__ void chain_step(const ChainParams& c, const double* f
 }
 
 // Called by every thread of every block after the block has written its
-// partial (NB x (1 + K) doubles at partials + blockIdx.x * NB * (1 + K)).
-// NT is the block size (a power of two).
+// partial (NB x (1 + K) doubles at partials + blk * NB * (1 + K), blk being
+// the block's index among the p.nblocks blocks of this evaluation).  NT is
+// the block size (a power of two).
 template <int NT, int NB>
-__device__ __forceinline__ void merge_partials(const FgParams& p) {
+__device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     __shared__ unsigned s_last;
     __shared__ double s_red[NT];
     const int K1 = p.K + 1;
     const int W = NB * K1;           // doubles per partial
-    const int grp = blockIdx.x / p.group;
+    const int grp = blk / p.group;
     const int b0 = grp * p.group;
     const int b1 = min(p.nblocks, b0 + p.group);
     const int ngroups = (p.nblocks + p.group - 1) / p.group;
@@ -427,6 +428,12 @@ struct WaveTile {
     static constexpr int OWN = R >= LPR ? R / LPR : 1;   // rows owned per lane after reduction
     static constexpr int REP = R >= LPR ? 1 : LPR / R;   // lanes sharing one owned row
     static constexpr int RBUF = NB * RPW * R;     // LDS values per wave for r
+    // With several coefficient vectors and rows shared by REP lanes, the REP
+    // lanes of a row split its NB per-row maps between them (lane cl % REP
+    // takes slots cl % REP, cl % REP + REP, ...) instead of each repeating
+    // all of them; NTR is the number of maps a lane then evaluates.
+    static constexpr bool SPLIT_TR = REP > 1 && NB > 1;
+    static constexpr int NTR = SPLIT_TR ? (NB + REP - 1) / REP : 1;
     using rtype = typename std::conditional<F64, double, float>::type;
 
     struct Tile {
@@ -447,6 +454,7 @@ struct WaveTile {
     double bd[NB][CPL][VE];                   // beta (FP64 storage)
     double g64[NB][CPL][VE];                  // this lane's gradient columns
     double facc[NB];
+    double fk[NTR];                           // f of slot cl % REP + k * REP (SPLIT_TR)
 
     __device__ __forceinline__ void init(int lane_, int K, int64_t ldx, int family) {
         lane = lane_;
@@ -514,6 +522,8 @@ struct WaveTile {
                 for (int e = 0; e < VE; ++e) g64[b][i][e] = 0.0;
             facc[b] = 0.0;
         }
+#pragma unroll
+        for (int k = 0; k < NTR; ++k) fk[k] = 0.0;
     }
 
     // Loads the batch of rows row0 .. row0 + BATCH - 1 of a row block whose
@@ -557,6 +567,9 @@ struct WaveTile {
 #pragma unroll
                 for (int i = 0; i < CPL; ++i) t.x[j][i] &= xmask[i];
         }
+        double ub[NB];   // the owned row's u per slot (SPLIT_TR)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) ub[b] = 0.0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             if (b >= nact) break;
@@ -600,6 +613,10 @@ struct WaveTile {
 #pragma unroll
                 for (int o = 0; o < OWN; ++o) uo[o] = (double)v[o].h + (double)v[o].l;
             }
+            if constexpr (SPLIT_TR) {
+                ub[b] = uo[0];
+                continue;
+            }
             // TR map on owned rows (FP64); r to the segment through LDS
 #pragma unroll
             for (int o = 0; o < OWN; ++o) {
@@ -611,6 +628,25 @@ struct WaveTile {
                     wout[row0 + yoff[o]] = tr_weight(uo[o], fam);
                 if (unique) {
                     const int j = R >= LPR ? cl * OWN + o : cl / REP;
+                    rbuf[(b * RPW + seg) * R + j] = ok ? (rtype)rr : (rtype)0;
+                }
+            }
+        }
+        if constexpr (SPLIT_TR) {
+            // one owned row (OWN == 1), its maps split over the REP lanes
+            const int sub = cl % REP;
+            const int j = cl / REP;
+            const bool ok = yoff[0] < nvalid;
+#pragma unroll
+            for (int k = 0; k < NTR; ++k) {
+                const int b = sub + k * REP;
+                if (b < nact) {
+                    double u = ub[0];
+#pragma unroll
+                    for (int bb = 1; bb < NB; ++bb) u = b == bb ? ub[bb] : u;
+                    double tt, rr;
+                    tr_map(u, t.yb[0], fam, tt, rr);
+                    if (ok) fk[k] += tt;
                     rbuf[(b * RPW + seg) * R + j] = ok ? (rtype)rr : (rtype)0;
                 }
             }
@@ -679,6 +715,16 @@ struct WaveTile {
     // Column sums over the segments of the wave (every lane of segment 0
     // ends with its columns' totals) and the wave totals of f (every lane).
     __device__ __forceinline__ void wave_totals() {
+        if constexpr (SPLIT_TR) {
+            const int sub = cl % REP;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < NTR; ++k) v = sub + k * REP == b ? fk[k] : v;
+                facc[b] = v;
+            }
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -693,9 +739,10 @@ struct WaveTile {
 
 // ------------------------------------------------------------ plain kernel
 
-// f and g of p.nb (<= NB) coefficient vectors over all rows of one data set.
-template <int DT, int LPR, int CPL, int R, int WPB, int NB = 1>
-__global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
+// Block blk (of p.nblocks) of the evaluation of f and g of p.nb (<= NB)
+// coefficient vectors over all rows of one data set.
+template <int DT, int LPR, int CPL, int R, int WPB, int NB>
+__device__ __forceinline__ void fg_pass(const FgParams& p, const int blk) {
     using WT = WaveTile<DT, LPR, CPL, R, NB>;
     constexpr int BATCH = WT::BATCH;
     constexpr int KT = WT::KT;
@@ -729,8 +776,8 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
     // grid-strided (all waves sweep memory together) or one contiguous,
     // balanced range per wave.
     const int64_t nbatch = (p.N + BATCH - 1) / BATCH;
-    const int64_t tw = (int64_t)gridDim.x * WPB;
-    const int64_t gw = (int64_t)blockIdx.x * WPB + wave;
+    const int64_t tw = (int64_t)p.nblocks * WPB;
+    const int64_t gw = (int64_t)blk * WPB + wave;
     if (p.interleave) {
         typename WT::Tile ta, tb;
         const int64_t step = tw * BATCH;
@@ -774,7 +821,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
         }
         __syncthreads();
     }
-    double* part = p.partials + (int64_t)blockIdx.x * NB * K1;
+    double* part = p.partials + (int64_t)blk * NB * K1;
     for (int b = 0; b < NB; ++b) {
         for (int k = threadIdx.x; k < p.K; k += blockDim.x) {
             double sacc = gsh[b][k];
@@ -788,7 +835,35 @@ __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
             part[b * K1] = sacc;
         }
     }
-    merge_partials<WPB * 64, NB>(p);
+    merge_partials<WPB * 64, NB>(p, blk);
+}
+
+// f and g of p.nb (<= NB) coefficient vectors over all rows of one data set
+// (the grid is p.nblocks blocks).
+template <int DT, int LPR, int CPL, int R, int WPB, int NB = 1>
+__global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
+    fg_pass<DT, LPR, CPL, R, WPB, NB>(p, blockIdx.x);
+}
+
+// ------------------------------------------------------------ fleet kernel
+
+// One evaluation of a fleet launch: the parameters of a several-beta pass
+// over one data set and the first of its consecutive blocks in the grid.
+struct FleetJob {
+    FgParams p;
+    int blk0;
+    int pad_;
+};
+
+// Several data sets of one kernel geometry in one launch: block b works on
+// job blk_job[b] as block b - blk0 of that job's own grid, so every job runs
+// exactly the blocks, row ranges and merge order of a launch of its own and
+// its results are bitwise those of fg_fused over the same parameters.
+template <int DT, int LPR, int CPL, int R, int WPB, int NB>
+__global__ __launch_bounds__(WPB * 64) void fg_fleet(const FleetJob* jobs, const uint16_t* blk_job) {
+    const int j = blk_job[blockIdx.x];
+    const FgParams p = jobs[j].p;
+    fg_pass<DT, LPR, CPL, R, WPB, NB>(p, (int)blockIdx.x - jobs[j].blk0);
 }
 
 }  // namespace glmk

@@ -1,5 +1,7 @@
-// Several coefficient vectors per pass over X: the kernel instances, and the
-// public entry point glm_logpost_grad_multi.
+// Several coefficient vectors per pass over X: the kernel instances (one
+// data set per launch, and the fleet form that runs the passes of several
+// data sets of one geometry in one launch), and the public entry point
+// glm_logpost_grad_multi.
 #include "fg_kernel.hpp"
 #include "runtime.hpp"
 
@@ -17,7 +19,8 @@ MultiInst minst() {
     if constexpr (NB * CPL * VE > 32) {
         return MultiInst{};
     } else {
-        return MultiInst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 8, WPB, NB>), 8, NB};
+        return MultiInst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 8, WPB, NB>), 8, NB,
+                         reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 8, WPB, NB>)};
     }
 }
 
@@ -65,6 +68,13 @@ MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max) {
         if (m.fn) return m;
     }
     return MultiInst{};
+}
+
+glm_status launch_fleet(const void* fn, int nblocks, const glmk::FleetJob* jobs,
+                        const uint16_t* blk_job, hipStream_t stream) {
+    void* args[] = {&jobs, &blk_job};
+    GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(nblocks), dim3(WPB * 64), args, 0, stream));
+    return GLM_OK;
 }
 
 }  // namespace glmrt

@@ -112,11 +112,11 @@ void scratch_need(const Plan& pl, int K, int NB, size_t* n_partials, size_t* n_g
     *n_counters = (size_t)ngroups + 1;
 }
 
-glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
-                        const double* betas, const double* means, const double* precs,
-                        double prec, int nb, double* out, Scratch* s, hipStream_t stream,
-                        double* w_out, const void* chain) {
-    glmk::FgParams p;
+void fused_params(const glm_dataset_desc& d, const Plan& pl, int NB, const double* betas,
+                  const double* means, const double* precs, double prec, int nb, double* out,
+                  double* partials, double* gpart, unsigned* counters, double* w_out,
+                  const void* chain, glmk::FgParams* pp) {
+    glmk::FgParams& p = *pp;
     p.X = static_cast<const unsigned char*>(d.X);
     p.ldx = d.ldx;
     p.y = d.y;
@@ -129,15 +129,24 @@ glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* f
     p.precs = precs;
     p.nb = nb;
     p.out = out;
-    p.partials = s->partials;
-    p.gpart = s->gpart;
-    p.counters = s->counters;
+    p.partials = partials;
+    p.gpart = gpart;
+    p.counters = counters;
     p.nblocks = pl.nblocks;
     p.group = pl.group;
     p.interleave = pl.interleave;
     p.family = d.family;
     p.w_out = NB == 1 ? w_out : nullptr;
     p.chain = NB == 1 ? static_cast<const glmk::ChainParams*>(chain) : nullptr;
+}
+
+glm_status launch_fused(const glm_dataset_desc& d, const Plan& pl, const void* fn, int NB,
+                        const double* betas, const double* means, const double* precs,
+                        double prec, int nb, double* out, Scratch* s, hipStream_t stream,
+                        double* w_out, const void* chain) {
+    glmk::FgParams p;
+    fused_params(d, pl, NB, betas, means, precs, prec, nb, out, s->partials, s->gpart, s->counters,
+                 w_out, chain, &p);
     void* args[] = {&p};
     GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(pl.nblocks), dim3(pl.wpb * 64), args, 0, stream));
     return GLM_OK;

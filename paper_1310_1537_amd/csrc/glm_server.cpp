@@ -1,13 +1,18 @@
 // Request server: many MCMC chains submit f + g requests for data sets kept
 // resident in HBM; a scheduler thread batches requests of the same data set
-// into one several-beta pass over X and keeps up to n_slots passes in flight
-// on n_streams streams (continuous batching: requests that arrive while
-// passes run are packed into the next free slot).  Data sets are admitted to
-// device memory on first use within an HBM budget, evicting the least
-// recently used idle ones when needed.
+// into one several-beta pass over X and keeps up to n_slots launches in
+// flight on n_streams streams (continuous batching: requests that arrive
+// while passes run are packed into the next free slot).  Data sets are
+// admitted to device memory on first use within an HBM budget, evicting the
+// least recently used idle ones when needed.
 //
 // The offload cost of a host-driven call is the reason for this design
-// (Sec. 4.5): one transfer + launch pays for up to NB evaluations.
+// (Sec. 4.5): one transfer + launch pays for up to NB evaluations.  A small
+// data set's pass is bound by latency (a few dependent memory round trips
+// and the cross-block merge), not by its bytes, so the passes of every data
+// set of one kernel geometry that has requests queued share one launch (a
+// fleet launch): each keeps its own blocks, rows and merge order, so its
+// results are bitwise those of a launch of its own.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -18,6 +23,7 @@
 #include <thread>
 #include <unordered_map>
 
+#include "fg_kernel.hpp"
 #include "runtime.hpp"
 
 using Clock = std::chrono::steady_clock;
@@ -55,20 +61,29 @@ struct SDataset {
     MultiInst mi;             // several-beta instance (or plan.fn with NB = 1)
 };
 
+// One data set's pass within a launch.
+struct SlotJob {
+    int64_t ds;
+    int nb;
+    int K;
+    size_t out_off;   // doubles into the slot's result area
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    int64_t ds = 0;
-    int nb = 0;
-    std::vector<uint64_t> tickets;
+    std::vector<SlotJob> jobs;
+    std::vector<uint64_t> tickets;            // in job order
     std::vector<Clock::time_point> t_submit;
-    // staging: [betas NB*K][means NB*K][precs NB] in, [NB*(K+1)] out
-    double* h_in = nullptr;
+    // staging in: [fleet jobs][block -> job table][per job: betas nb x K,
+    // precisions nb, means nb x K if any request has one]; out: per job
+    // nb x (K + 1) doubles, written by the kernel into coherent pinned host
+    // memory (no device-to-host copy per launch)
+    unsigned char* h_in = nullptr;
+    unsigned char* d_in = nullptr;
     double* h_out = nullptr;
-    double* d_in = nullptr;
-    double* d_out = nullptr;
-    size_t cap_in = 0, cap_out = 0;   // doubles
+    size_t cap_in = 0, cap_out = 0;   // bytes, doubles
     Scratch scratch;
 };
 
@@ -97,7 +112,8 @@ struct glm_server {
     size_t resident_bytes = 0;
     // statistics
     uint64_t submitted = 0, completed = 0, cancelled = 0, failed = 0;
-    uint64_t passes = 0, betas_in_passes = 0, admissions = 0, evictions = 0;
+    uint64_t passes = 0, betas_in_passes = 0, admissions = 0, evictions = 0, launches = 0;
+    int max_sets = 32;   // data sets per launch at most
     uint64_t hist[9] = {0};
     std::vector<float> lat_us;   // submit -> completion of finished requests
     std::string sched_error;
@@ -166,31 +182,36 @@ int admit(glm_server* s, SDataset& ds) {
     return 1;
 }
 
-bool ensure_slot_capacity(Slot& sl, int NB, int K, const Plan& pl) {
-    const size_t need_in = (size_t)NB * (2 * K + 1), need_out = (size_t)NB * (K + 1);
-    if (sl.cap_in < need_in || sl.cap_out < need_out) {
+// Grows the slot's staging areas and scratch to at least the given sizes
+// (with headroom, so that growth is rare; the slot is idle when called).
+bool ensure_slot_capacity(Slot& sl, size_t in_bytes, size_t out_doubles, size_t np, size_t ng,
+                          size_t nc) {
+    if (sl.cap_in < in_bytes) {
+        const size_t cap = std::max(in_bytes + in_bytes / 2, (size_t)1 << 16);
         if (sl.h_in) (void)hipHostFree(sl.h_in);
-        if (sl.h_out) (void)hipHostFree(sl.h_out);
         if (sl.d_in) (void)hipFree(sl.d_in);
-        sl.h_in = sl.h_out = sl.d_in = nullptr;
-        sl.d_out = nullptr;
-        sl.cap_in = sl.cap_out = 0;
-        if (hipHostMalloc((void**)&sl.h_in, need_in * 8) != hipSuccess) return false;
-        // results are written by the kernel straight into coherent pinned host
-        // memory (no device-to-host copy per pass)
-        if (hipHostMalloc((void**)&sl.h_out, need_out * 8, hipHostMallocCoherent) != hipSuccess)
-            return false;
-        if (hipMalloc((void**)&sl.d_in, (need_in + need_out) * 8) != hipSuccess) return false;
-        sl.d_out = sl.d_in + need_in;
-        sl.cap_in = need_in;
-        sl.cap_out = need_out;
+        sl.h_in = sl.d_in = nullptr;
+        sl.cap_in = 0;
+        if (hipHostMalloc((void**)&sl.h_in, cap) != hipSuccess) return false;
+        if (hipMalloc((void**)&sl.d_in, cap) != hipSuccess) return false;
+        sl.cap_in = cap;
     }
-    size_t np, ng, nc;
-    scratch_need(pl, K, NB, &np, &ng, &nc);
+    if (sl.cap_out < out_doubles) {
+        const size_t cap = std::max(out_doubles + out_doubles / 2, (size_t)4096);
+        if (sl.h_out) (void)hipHostFree(sl.h_out);
+        sl.h_out = nullptr;
+        sl.cap_out = 0;
+        if (hipHostMalloc((void**)&sl.h_out, cap * 8, hipHostMallocCoherent) != hipSuccess)
+            return false;
+        sl.cap_out = cap;
+    }
     Scratch& sc = sl.scratch;
     if (!sc.base || sc.cap_partials < np || sc.cap_gpart < ng || sc.cap_counters < nc) {
         if (sc.base) (void)hipFree(sc.base);
         sc = Scratch{};
+        np += np / 2;
+        ng += ng / 2;
+        nc += nc / 2 + 64;
         const size_t bytes = (np + ng) * 8 + nc * 4;
         if (hipMalloc(&sc.base, bytes) != hipSuccess) return false;
         sc.partials = (double*)sc.base;
@@ -199,30 +220,33 @@ bool ensure_slot_capacity(Slot& sl, int NB, int K, const Plan& pl) {
         sc.cap_partials = np;
         sc.cap_gpart = ng;
         sc.cap_counters = nc;
+        // tickets start at zero; every launch leaves the ones it used at zero
         if (hipMemsetAsync(sc.counters, 0, nc * 4, sl.stream) != hipSuccess) return false;
     }
     return true;
 }
 
-// Completes finished passes; returns true if any finished.
+// Completes finished launches; returns true if any finished.
 bool reap(glm_server* s) {
     bool any = false;
     for (Slot& sl : s->slots) {
         if (!sl.busy || hipEventQuery(sl.done) != hipSuccess) continue;
         const Clock::time_point now = Clock::now();
         std::lock_guard<std::mutex> lk(s->mu);
-        SDataset& ds = s->datasets[sl.ds];
-        const int K = ds.src.K;
-        for (int i = 0; i < sl.nb; ++i) {
-            Result& r = s->results[sl.tickets[i]];
-            r.state = R_DONE;
-            r.f = sl.h_out[(size_t)i * (K + 1)];
-            r.g.assign(sl.h_out + (size_t)i * (K + 1) + 1, sl.h_out + (size_t)(i + 1) * (K + 1));
-            s->lat_us.push_back(
-                (float)std::chrono::duration<double, std::micro>(now - sl.t_submit[i]).count());
+        size_t t = 0;
+        for (const SlotJob& j : sl.jobs) {
+            const double* o = sl.h_out + j.out_off;
+            for (int i = 0; i < j.nb; ++i, ++t) {
+                Result& r = s->results[sl.tickets[t]];
+                r.state = R_DONE;
+                r.f = o[(size_t)i * (j.K + 1)];
+                r.g.assign(o + (size_t)i * (j.K + 1) + 1, o + (size_t)(i + 1) * (j.K + 1));
+                s->lat_us.push_back(
+                    (float)std::chrono::duration<double, std::micro>(now - sl.t_submit[t]).count());
+            }
+            s->datasets[j.ds].inflight--;
         }
-        s->completed += sl.nb;
-        ds.inflight--;
+        s->completed += t;
         sl.busy = false;
         any = true;
     }
@@ -230,9 +254,30 @@ bool reap(glm_server* s) {
     return any;
 }
 
-// Starts at most one pass on a free slot; returns true if it did.  The data
-// set whose oldest queued request is oldest goes first (FIFO across data
-// sets); data sets that must wait for memory are skipped.
+// Fails every queued request of a data set (its admission failed).
+void fail_queue(glm_server* s, int64_t dsid) {
+    auto& q = s->pending[dsid];
+    for (Request& r : q) {
+        s->results[r.ticket].state = R_FAILED;
+        s->failed++;
+    }
+    s->queued -= q.size();
+    q.clear();
+    s->cv.notify_all();
+}
+
+// A data set chosen for a launch with the requests it takes.
+struct Pick {
+    int64_t id;
+    SDataset* ds;
+    std::vector<Request> reqs;
+};
+
+// Starts at most one launch on a free slot; returns true if it did (or if it
+// failed requests).  The data set whose oldest queued request is oldest goes
+// first (FIFO across data sets); the other data sets of its kernel geometry
+// with queued requests join it in the same order, up to max_sets_per_pass;
+// data sets that must wait for memory are skipped.
 bool dispatch(glm_server* s) {
     Slot* sl = nullptr;
     for (Slot& c : s->slots)
@@ -241,9 +286,7 @@ bool dispatch(glm_server* s) {
             break;
         }
     if (!sl) return false;
-    std::vector<Request> batch;
-    SDataset* dsp = nullptr;
-    int64_t dsid = 0;
+    std::vector<Pick> picks;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->queued == 0) return false;
@@ -251,91 +294,150 @@ bool dispatch(glm_server* s) {
         for (auto& kv : s->pending)
             if (!kv.second.empty()) heads.push_back({kv.second.front().t_submit, kv.first});
         std::sort(heads.begin(), heads.end());
+        const void* fleet = nullptr;
+        bool failed = false;
         for (auto& h : heads) {
             SDataset& ds = s->datasets[h.second];
+            if (!picks.empty() && !fleet) break;
+            if (!picks.empty() && ds.mi.fleet != fleet) continue;
             const int a = admit(s, ds);
             if (a < 0) {
-                // fail every queued request of this data set
-                auto& q = s->pending[h.second];
-                for (Request& r : q) {
-                    s->results[r.ticket].state = R_FAILED;
-                    s->failed++;
-                }
-                s->queued -= q.size();
-                q.clear();
-                s->cv.notify_all();
-                return true;
+                fail_queue(s, h.second);
+                failed = true;
+                continue;
             }
             if (a == 0) continue;
-            dsp = &ds;
-            dsid = h.second;
-            break;
+            const int NB = ds.mi.fn ? ds.mi.NB : 1;
+            Pick pk{h.second, &ds, {}};
+            auto& q = s->pending[h.second];
+            while (!q.empty() && (int)pk.reqs.size() < NB) {
+                pk.reqs.push_back(std::move(q.front()));
+                q.pop_front();
+            }
+            s->queued -= pk.reqs.size();
+            ds.inflight++;   // also keeps it from being evicted by a later admission
+            ds.last_use = ++s->use_clock;
+            if (picks.empty()) fleet = s->max_sets > 1 ? ds.mi.fleet : nullptr;
+            picks.push_back(std::move(pk));
+            if ((int)picks.size() >= s->max_sets) break;
         }
-        if (!dsp) return false;
-        const int NB = dsp->mi.fn ? dsp->mi.NB : 1;
-        auto& q = s->pending[dsid];
-        while (!q.empty() && (int)batch.size() < NB) {
-            batch.push_back(std::move(q.front()));
-            q.pop_front();
-        }
-        s->queued -= batch.size();
-        dsp->inflight++;
-        dsp->last_use = ++s->use_clock;
+        if (picks.empty()) return failed;
     }
-    SDataset& ds = *dsp;
-    const int K = ds.src.K;
-    const int NB = ds.mi.fn ? ds.mi.NB : 1;
-    const void* fn = ds.mi.fn ? ds.mi.fn : ds.plan.fn;
-    const int nb = (int)batch.size();
-    bool ok = ensure_slot_capacity(*sl, NB, K, ds.plan);
-    bool has_mean = false;
-    for (const Request& r : batch) has_mean |= r.has_mean;
+    // small grids first: their dependent round trips start at once
+    std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) {
+        return a.ds->plan.nblocks < b.ds->plan.nblocks;
+    });
+    const int nj = (int)picks.size();
+    const bool use_fleet = nj > 1;
+    const SDataset& d0 = *picks[0].ds;
+    const int NB = d0.mi.fn ? d0.mi.NB : 1;
+
+    // layout of the staging and scratch areas
+    std::vector<size_t> in_off(nj), out_off(nj), p_off(nj), g_off(nj), c_off(nj);
+    std::vector<bool> has_mean(nj, false);
+    int grid = 0;
+    for (int j = 0; j < nj; ++j) grid += picks[j].ds->plan.nblocks;
+    size_t in_bytes = use_fleet ? (size_t)nj * sizeof(glmk::FleetJob) : 0;
+    if (use_fleet) in_bytes += ((size_t)grid * 2 + 7) / 8 * 8;
+    size_t out_d = 0, np = 0, ng = 0, nc = 0;
+    for (int j = 0; j < nj; ++j) {
+        const Pick& pk = picks[j];
+        const int K = pk.ds->src.K, nb = (int)pk.reqs.size();
+        for (const Request& r : pk.reqs) has_mean[j] = has_mean[j] || r.has_mean;
+        in_off[j] = in_bytes;
+        in_bytes += ((size_t)nb * K + nb + (has_mean[j] ? (size_t)nb * K : 0)) * 8;
+        out_off[j] = out_d;
+        out_d += (size_t)nb * (K + 1);
+        size_t a, b, c;
+        scratch_need(pk.ds->plan, K, NB, &a, &b, &c);
+        p_off[j] = np;
+        g_off[j] = ng;
+        c_off[j] = nc;
+        np += a;
+        ng += b;
+        nc += c;
+    }
+    bool ok = ensure_slot_capacity(*sl, in_bytes, out_d, np, ng, nc);
     if (ok) {
-        // one host-to-device copy per pass: betas (nb x K), precisions (nb),
-        // then the means (nb x K) when any request has one
-        double* hb = sl->h_in;
-        double* hp = hb + (size_t)nb * K;
-        double* hm = hp + nb;
-        for (int i = 0; i < nb; ++i) {
-            std::memcpy(hb + (size_t)i * K, batch[i].beta.data(), K * 8);
-            hp[i] = batch[i].prec;
-            if (has_mean) {
-                if (batch[i].has_mean)
-                    std::memcpy(hm + (size_t)i * K, batch[i].mean.data(), K * 8);
-                else
-                    std::fill(hm + (size_t)i * K, hm + (size_t)(i + 1) * K, 0.0);
+        unsigned char* h = sl->h_in;
+        std::vector<glmk::FgParams> prm(nj);
+        for (int j = 0; j < nj; ++j) {
+            const Pick& pk = picks[j];
+            const int K = pk.ds->src.K, nb = (int)pk.reqs.size();
+            double* hb = (double*)(h + in_off[j]);
+            double* hp = hb + (size_t)nb * K;
+            double* hm = hp + nb;
+            for (int i = 0; i < nb; ++i) {
+                const Request& r = pk.reqs[i];
+                std::memcpy(hb + (size_t)i * K, r.beta.data(), K * 8);
+                hp[i] = r.prec;
+                if (has_mean[j]) {
+                    if (r.has_mean)
+                        std::memcpy(hm + (size_t)i * K, r.mean.data(), K * 8);
+                    else
+                        std::fill(hm + (size_t)i * K, hm + (size_t)(i + 1) * K, 0.0);
+                }
+            }
+            const double* db = (const double*)(sl->d_in + in_off[j]);
+            fused_params(pk.ds->dev, pk.ds->plan, NB, db, has_mean[j] ? db + (size_t)nb * K + nb : nullptr,
+                         db + (size_t)nb * K, 0.0, nb, sl->h_out + out_off[j],
+                         sl->scratch.partials + p_off[j], sl->scratch.gpart + g_off[j],
+                         sl->scratch.counters + c_off[j], nullptr, nullptr, &prm[j]);
+        }
+        if (use_fleet) {
+            glmk::FleetJob* fj = (glmk::FleetJob*)h;
+            uint16_t* bj = (uint16_t*)(h + (size_t)nj * sizeof(glmk::FleetJob));
+            int b = 0;
+            for (int j = 0; j < nj; ++j) {
+                fj[j].p = prm[j];
+                fj[j].blk0 = b;
+                fj[j].pad_ = 0;
+                for (int k = 0; k < prm[j].nblocks; ++k) bj[b++] = (uint16_t)j;
             }
         }
-        const size_t words = (size_t)nb * K + nb + (has_mean ? (size_t)nb * K : 0);
-        ok = hipMemcpyAsync(sl->d_in, hb, words * 8, hipMemcpyHostToDevice, sl->stream) == hipSuccess;
-        if (ok)
-            ok = launch_fused(ds.dev, ds.plan, fn, NB, sl->d_in,
-                              has_mean ? sl->d_in + (size_t)nb * K + nb : nullptr,
-                              sl->d_in + (size_t)nb * K, 0.0, nb, sl->h_out, &sl->scratch,
-                              sl->stream) == GLM_OK;
+        ok = hipMemcpyAsync(sl->d_in, h, in_bytes, hipMemcpyHostToDevice, sl->stream) == hipSuccess;
+        if (ok) {
+            if (use_fleet) {
+                ok = launch_fleet(d0.mi.fleet, grid, (const glmk::FleetJob*)sl->d_in,
+                                  (const uint16_t*)(sl->d_in + (size_t)nj * sizeof(glmk::FleetJob)),
+                                  sl->stream) == GLM_OK;
+            } else {
+                const void* fn = d0.mi.fn ? d0.mi.fn : d0.plan.fn;
+                void* args[] = {&prm[0]};
+                ok = hipLaunchKernel(fn, dim3(d0.plan.nblocks), dim3(d0.plan.wpb * 64), args, 0,
+                                     sl->stream) == hipSuccess;
+            }
+        }
         if (ok) ok = hipEventRecord(sl->done, sl->stream) == hipSuccess;
     }
     std::lock_guard<std::mutex> lk(s->mu);
     if (!ok) {
-        for (const Request& r : batch) s->results[r.ticket].state = R_FAILED;
-        s->failed += nb;
-        ds.inflight--;
-        s->sched_error = "pass launch failed";
+        for (Pick& pk : picks) {
+            for (const Request& r : pk.reqs) s->results[r.ticket].state = R_FAILED;
+            s->failed += pk.reqs.size();
+            pk.ds->inflight--;
+        }
+        s->sched_error = "launch failed";
         s->cv.notify_all();
         return true;
     }
     sl->busy = true;
-    sl->ds = dsid;
-    sl->nb = nb;
+    sl->jobs.clear();
     sl->tickets.clear();
     sl->t_submit.clear();
-    for (const Request& r : batch) {
-        sl->tickets.push_back(r.ticket);
-        sl->t_submit.push_back(r.t_submit);
+    for (int j = 0; j < nj; ++j) {
+        const Pick& pk = picks[j];
+        const int nb = (int)pk.reqs.size();
+        sl->jobs.push_back(SlotJob{pk.id, nb, pk.ds->src.K, out_off[j]});
+        for (const Request& r : pk.reqs) {
+            sl->tickets.push_back(r.ticket);
+            sl->t_submit.push_back(r.t_submit);
+        }
+        s->passes++;
+        s->betas_in_passes += nb;
+        s->hist[std::min(nb, 8)]++;
     }
-    s->passes++;
-    s->betas_in_passes += nb;
-    s->hist[std::min(nb, 8)]++;
+    s->launches++;
     return true;
 }
 
@@ -369,11 +471,15 @@ glm_status glm_server_create(glm_ctx* ctx, const glm_server_config* cfg, glm_ser
     *out = nullptr;
     if (cfg->max_beta_per_pass < 1 || cfg->n_streams < 1 || cfg->n_slots < 1 || cfg->queue_capacity < 1)
         GLM_FAIL(GLM_EINVAL, "glm_server_create: counts must be >= 1");
+    if (cfg->max_sets_per_pass < 0 || cfg->max_sets_per_pass > 256)
+        GLM_FAIL(GLM_EINVAL, "glm_server_create: max_sets_per_pass = %d not in 0..256",
+                 cfg->max_sets_per_pass);
     glm_status st = use_device(ctx);
     if (st != GLM_OK) return st;
     std::unique_ptr<glm_server> s(new glm_server);
     s->ctx = ctx;
     s->cfg = *cfg;
+    s->max_sets = cfg->max_sets_per_pass ? cfg->max_sets_per_pass : 32;
     s->streams.resize(cfg->n_streams);
     for (auto& st_ : s->streams) GLM_HIP_CHECK(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
     s->slots.resize(cfg->n_slots);
@@ -563,6 +669,7 @@ glm_status glm_server_stats(glm_server* s, glm_server_metrics* out) {
     out->cancelled = s->cancelled;
     out->failed = s->failed;
     out->passes = s->passes;
+    out->launches = s->launches;
     out->betas_in_passes = s->betas_in_passes;
     out->admissions = s->admissions;
     out->evictions = s->evictions;
@@ -593,7 +700,7 @@ glm_status glm_server_reset_stats(glm_server* s) {
     if (!s) GLM_FAIL(GLM_EINVAL, "glm_server_reset_stats: NULL server");
     std::lock_guard<std::mutex> lk(s->mu);
     s->submitted = s->completed = s->cancelled = s->failed = 0;
-    s->passes = s->betas_in_passes = s->admissions = s->evictions = 0;
+    s->passes = s->betas_in_passes = s->admissions = s->evictions = s->launches = 0;
     std::memset(s->hist, 0, sizeof(s->hist));
     s->lat_us.clear();
     return GLM_OK;

@@ -144,8 +144,30 @@ struct MultiInst {
     const void* fn = nullptr;
     int R = 0;
     int NB = 0;
+    const void* fleet = nullptr;   // the same geometry over several data sets per launch
 };
 MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max);
+
+}  // namespace glmrt
+namespace glmk {
+struct FgParams;
+struct FleetJob;
+}
+namespace glmrt {
+
+// The kernel parameters launch_fused passes (partials, gpart and counters
+// being the scratch regions of one evaluation).
+void fused_params(const glm_dataset_desc& d, const Plan& pl, int NB, const double* betas,
+                  const double* means, const double* precs, double prec, int nb, double* out,
+                  double* partials, double* gpart, unsigned* counters, double* w_out,
+                  const void* chain, glmk::FgParams* p);
+
+// Launches a fleet instance (MultiInst::fleet) over nblocks blocks: jobs and
+// blk_job (one job index per block) in device memory; every job's parameters
+// are those launch_fused would pass for its data set, with blk0 its first
+// block.
+glm_status launch_fleet(const void* fn, int nblocks, const glmk::FleetJob* jobs,
+                        const uint16_t* blk_job, hipStream_t stream);
 
 // Launches a fused kernel instance (NB slots) for nb coefficient vectors
 // (betas nb x K, means nb x K or nullptr, precs nb or nullptr -> prec) into

@@ -53,7 +53,7 @@ class glm_groupset_info_t(ctypes.Structure):
 class glm_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_beta_per_pass", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("n_slots", ctypes.c_int32),
-                ("queue_capacity", ctypes.c_int32)]
+                ("queue_capacity", ctypes.c_int32), ("max_sets_per_pass", ctypes.c_int32)]
 
 
 class glm_server_stats_t(ctypes.Structure):
@@ -64,7 +64,7 @@ class glm_server_stats_t(ctypes.Structure):
                 ("resident_bytes", ctypes.c_uint64), ("resident_datasets", ctypes.c_int32),
                 ("queue_depth", ctypes.c_int32), ("pass_width_hist", ctypes.c_uint64 * 9),
                 ("latency_p50_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
-                ("latency_mean_us", ctypes.c_double)]
+                ("latency_mean_us", ctypes.c_double), ("launches", ctypes.c_uint64)]
 
 
 class glm_colset_desc(ctypes.Structure):
@@ -351,9 +351,10 @@ def glm_logpost_grad_batched(ctx: int, gs: int, betas, prior: glm_prior, out, st
 # ---------------------------------------------------------------- server
 
 def glm_server_create(ctx: int, hbm_budget_bytes: int, max_beta_per_pass: int = 8,
-                      n_streams: int = 4, n_slots: int = 8, queue_capacity: int = 1 << 20) -> int:
+                      n_streams: int = 4, n_slots: int = 8, queue_capacity: int = 1 << 20,
+                      max_sets_per_pass: int = 0) -> int:
     cfg = glm_server_config(hbm_budget_bytes, max_beta_per_pass, n_streams, n_slots,
-                            queue_capacity)
+                            queue_capacity, max_sets_per_pass)
     out = ctypes.c_void_p()
     _check(_lib.glm_server_create(ctx, ctypes.byref(cfg), ctypes.byref(out)))
     return out.value

@@ -95,8 +95,8 @@ def test_multi_result_independent_of_companions(ctx):
 
 # ------------------------------------------------------------------ server
 
-def _server(ctx, budget=1 << 34, nbmax=8, slots=8, streams=4, qcap=1 << 20):
-    return glm.glm_server_create(ctx, budget, nbmax, streams, slots, qcap)
+def _server(ctx, budget=1 << 34, nbmax=8, slots=8, streams=4, qcap=1 << 20, max_sets=0):
+    return glm.glm_server_create(ctx, budget, nbmax, streams, slots, qcap, max_sets)
 
 
 def test_server_results_match_oracle(ctx):
@@ -235,6 +235,68 @@ def test_server_device_resident_and_threads(ctx):
     for beta, f, g in list(res.values())[::10]:
         _check(f, g, X.astype(np.float64), y, beta, 0.01)
     glm.glm_server_destroy(srv)
+
+
+def _fleet_run(ctx, sets, reqs, max_sets):
+    """Serves reqs [(set index, beta)] on one slot, all submitted at once, so
+    that everything after the first launch is queued when the next one
+    starts."""
+    srv = _server(ctx, slots=1, streams=1, max_sets=max_sets)
+    ids = [glm.glm_server_add_dataset(srv, glm.make_desc(Xd, yd, dtype=dt), on_device=True)
+           for Xd, yd, dt in sets]
+    ptrs = np.array([b.ctypes.data for _, b in reqs], np.uint64)
+    t = glm.glm_server_submit_many(srv, np.array([ids[i] for i, _ in reqs], np.int64), ptrs,
+                                   np.full(len(reqs), 0.01))
+    out = []
+    for k in range(len(reqs)):
+        g = np.empty(len(reqs[k][1]))
+        f = glm.glm_server_wait(srv, int(t[k]), g)
+        out.append((f, g))
+    st = glm.glm_server_stats(srv)
+    glm.glm_server_destroy(srv)
+    return out, st
+
+
+def test_server_fleet_launch_bitwise_and_oracle(ctx):
+    """Passes of several data sets of one geometry (FP32, K = 32, N from 0 to
+    250,000) in one launch give the bits of one launch per data set, and
+    match the oracle; a BF16 K = 8 pair has another geometry and never shares
+    their launches."""
+    Ns = [700, 5_000, 0, 40_000, 250_000, 3_001, 64]
+    sets, host = [], []
+    for i, N in enumerate(Ns):
+        X, y, bt = _data(N, 32, 300 + i)
+        sets.append((to_dev(X), to_dev(y), glm.GLM_F32))
+        host.append((X.astype(np.float64), y, bt, None))
+    for i in range(2):
+        X, y, bt = _data(9_000 + 1_000 * i, 8, 320 + i)
+        Q = oracle.quantize_bf16(X)
+        sets.append((to_dev(Q), to_dev(y), glm.GLM_BF16))
+        host.append((oracle.decode_bf16(Q), y, bt, Q))
+    rng = np.random.default_rng(330)
+    reqs = []
+    for r in range(60):
+        i = int(rng.integers(0, len(sets)))
+        reqs.append((i, np.ascontiguousarray(host[i][2] + 0.1 * rng.standard_normal(len(host[i][2])))))
+    fleet, st = _fleet_run(ctx, sets, reqs, 0)
+    single, st1 = _fleet_run(ctx, sets, reqs, 1)
+    assert st["launches"] < st["passes"], st       # some launch carried several data sets
+    assert st1["launches"] == st1["passes"]
+    assert st["completed"] == st1["completed"] == len(reqs)
+    for (i, beta), (f, g), (f1, g1) in zip(reqs, fleet, single):
+        assert f == f1 and np.array_equal(g, g1), i
+        Xh, y, _, Q = host[i]
+        if Q is None:
+            _check(f, g, Xh, y, beta, 0.01)
+        else:
+            _check(f, g, Xh, y, beta, 0.01, Xo=Q, okw={"dtype": "bf16"})
+
+
+def test_server_max_sets_argument(ctx):
+    for bad in (-1, 257):
+        with pytest.raises(glm.GlmError) as e:
+            _server(ctx, max_sets=bad)
+        assert e.value.status == glm.GLM_EINVAL
 
 
 @pytest.mark.parametrize("K", [5, 100])
