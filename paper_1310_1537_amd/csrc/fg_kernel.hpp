@@ -293,6 +293,46 @@ __device__ __forceinline__ double ordered_sum(const double* a, int n, int64_t st
     return s;
 }
 
+// Buffer descriptor word 3 for raw (untyped) buffers on gfx9-class GPUs.
+constexpr int kRsrcWord3 = 0x00020000;
+
+// The same sums for the Q entries idx0 + q * step (q < Q) that are below lim
+// (the others give 0), with the loads of all Q issued before any addition:
+// one memory latency for Q entries instead of Q.  The loads go through a
+// buffer descriptor spanning the n x stride doubles, so the surplus ones
+// (past n, or an entry at or past lim, sent out of range) return zeros
+// without a branch; each sum is added in the order of ordered_sum (padding
+// included), so the results are bitwise equal.
+template <int Q>
+__device__ __forceinline__ void ordered_sums(const double* a, int n, int64_t stride, int idx0,
+                                             int step, int lim, double (&out)[Q]) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a, 0, (int)((int64_t)n * stride * 8), kRsrcWord3);
+    auto load = [&](int idx, int t) {
+        const uint32_t off = idx < lim ? (uint32_t)(idx + (int64_t)t * stride) * 8u : 0x80000000u;
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        return __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+    };
+    if (n == 1) {   // a single partial (one block, or one group)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) out[q] = 0.0 + load(idx0 + q * step, 0);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) out[q] = 0.0;
+    for (int t = 0; t < n; t += 16) {
+        double v[Q][16];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[q][j] = load(idx0 + q * step, t + j);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) out[q] += v[q][j];
+    }
+}
+
 // Accept iff log U_t < f(beta_prop) - f(beta); on acceptance the state takes
 // the proposal's beta, f and g; then beta_prop = beta + incs[t + 1] and t + 1.
 // Run by all threads of the last block after fg_prop (1 + K) is written.
@@ -331,7 +371,6 @@ __device__ __forceinline__ void chain_step(const ChainParams& c, const double* f
 template <int NT, int NB>
 __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     __shared__ unsigned s_last;
-    __shared__ double s_red[NT];
     const int K1 = p.K + 1;
     const int W = NB * K1;           // doubles per partial
     const int grp = blk / p.group;
@@ -352,8 +391,19 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     __syncthreads();
     if (!s_last) return;
 
-    for (int k = threadIdx.x; k < W; k += NT)
-        p.gpart[(int64_t)grp * W + k] = ordered_sum(p.partials + (int64_t)b0 * W + k, b1 - b0, W);
+    if (W <= NT) {   // one entry per thread
+        double v[1];
+        ordered_sums<1>(p.partials + (int64_t)b0 * W, b1 - b0, W, threadIdx.x, NT, W, v);
+        if ((int)threadIdx.x < W) p.gpart[(int64_t)grp * W + threadIdx.x] = v[0];
+    } else {
+        for (int k0 = threadIdx.x; k0 < W; k0 += 4 * NT) {
+            double v[4];
+            ordered_sums<4>(p.partials + (int64_t)b0 * W, b1 - b0, W, k0, NT, W, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (k0 + q * NT < W) p.gpart[(int64_t)grp * W + k0 + q * NT] = v[q];
+        }
+    }
     if (threadIdx.x == 0)
         __hip_atomic_store(&p.counters[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
@@ -372,32 +422,64 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     }
 
     // Final sums in group order, plus each slot's Gaussian prior N(m, prec^-1 I).
-    for (int b = 0; b < p.nb; ++b) {
-        const double* beta = p.beta + (int64_t)b * p.K;
-        const double* mean = p.mean ? p.mean + (int64_t)b * p.K : nullptr;
+    // The nb x (1 + K) entries are spread over the block, one per thread or,
+    // when there are more, four per thread and round (one memory latency per
+    // round); each slot's squared distance to
+    // its prior mean is summed per thread, then per wave (butterfly), then
+    // over the waves in order.
+    __shared__ double s_flik[NB];
+    __shared__ double s_pw[NT / 64][NB];
+    const int nbk = p.nb * K1;
+    double pf[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pf[b] = 0.0;
+    auto final_entry = [&](int idx, double sum) {
+        const int b = idx / K1, k = idx - b * K1;
+        if (k == 0) {
+            s_flik[b] = sum;   // likelihood part; prior added below
+            return;
+        }
         const double prec = p.precs ? p.precs[b] : p.prec;
-        double* out = p.out + (int64_t)b * K1;
-        double pf = 0.0;
-        double f_lik = 0.0;
-        for (int k = threadIdx.x; k < K1; k += NT) {
-            const double sacc = ordered_sum(p.gpart + (int64_t)b * K1 + k, ngroups, W);
-            if (k == 0) {
-                f_lik = sacc;   // likelihood part; prior added below
-            } else {
-                const double d = beta[k - 1] - (mean ? mean[k - 1] : 0.0);
-                pf += d * d;
-                out[k] = sacc - prec * d;
-            }
+        const int64_t bk = (int64_t)b * p.K + k - 1;
+        const double d = p.beta[bk] - (p.mean ? p.mean[bk] : 0.0);
+        p.out[(int64_t)b * K1 + k] = sum - prec * d;
+#pragma unroll
+        for (int bb = 0; bb < NB; ++bb)
+            if (bb == b) pf[bb] += d * d;
+    };
+    if (nbk <= NT) {   // one entry per thread
+        double sv[1];
+        ordered_sums<1>(p.gpart, ngroups, W, threadIdx.x, NT, nbk, sv);
+        if ((int)threadIdx.x < nbk) final_entry(threadIdx.x, sv[0]);
+    } else {
+        for (int i0 = threadIdx.x; i0 < nbk; i0 += 4 * NT) {
+            double sv[4];
+            ordered_sums<4>(p.gpart, ngroups, W, i0, NT, nbk, sv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i0 + q * NT < nbk) final_entry(i0 + q * NT, sv[q]);
         }
-        s_red[threadIdx.x] = pf;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[0] = f_lik - 0.5 * prec * s_red[0];
-        __syncthreads();
     }
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double v = pf[b];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+            if (lane == 0) s_pw[wave][b] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < p.nb) {
+        const int b = threadIdx.x;
+        double sq = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) sq += s_pw[w][b];
+        const double prec = p.precs ? p.precs[b] : p.prec;
+        p.out[(int64_t)b * K1] = s_flik[b] - 0.5 * prec * sq;
+    }
+    __syncthreads();
     if (p.chain) chain_step<NT>(*p.chain, p.out, p.K);
     if (threadIdx.x == 0)
         __hip_atomic_store(&p.counters[ngroups], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -405,8 +487,6 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
 
 // ------------------------------------------------------------ wave tiles
 
-// Buffer descriptor word 3 for raw (untyped) buffers on gfx9-class GPUs.
-constexpr int kRsrcWord3 = 0x00020000;
 // Cache policy of the streaming loads: nontemporal.
 constexpr int kLoadNT = 2;
 
