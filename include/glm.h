@@ -177,6 +177,10 @@ glm_status glm_logpost_grad(glm_ctx* ctx, glm_dataset_id id, const double* beta,
  * g for each of betas[0..nb-1], with X streamed once per pass of up to 8
  * vectors (the pass width is the largest of 8, 4, 2 that the instance's
  * register budget allows for this K and dtype; larger nb runs several passes).
+ * For BF16 storage with 65 <= K <= 512 and nb >= 4 a pass holds 4 vectors and
+ * their linear predictors X beta run on the matrix cores, with each beta
+ * split into four BF16 pieces (about 32 significant bits); the result has the
+ * accuracy of the other storage forms' FP32 hi/lo split.
  *   betas  device, nb x K doubles
  *   prior  host struct; prior->mean NULL (zero) or device nb x K doubles
  *          (row b is the mean for betas row b); prec shared

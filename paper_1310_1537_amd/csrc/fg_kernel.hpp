@@ -817,6 +817,55 @@ struct WaveTile {
     }
 };
 
+// ------------------------------------------------------------ block merge
+
+// The waves of a block add their column totals into one LDS vector in wave
+// order, the block writes its partial of NB x (1 + K) doubles and joins the
+// cross-block merge.  WT is the wave tile type: every lane of segment 0 holds
+// the totals of its columns col(i, e) in g64, every lane the wave's f per slot.
+template <class WT, int DT, int WPB, int NB>
+__device__ __forceinline__ void block_merge(const FgParams& p, const int blk, const WT& wt,
+                                            const int wave) {
+    constexpr int KT = WT::KT;
+    constexpr int VE = WT::VE;
+    constexpr int CPL = WT::CHUNKS;
+    const int K1 = p.K + 1;
+    __shared__ double gsh[NB][KT];
+    __shared__ double fsh[WPB][NB];
+    if (wt.lane == 0)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) fsh[wave][b] = wt.facc[b];
+    for (int w = 0; w < WPB; ++w) {
+        if (wave == w && wt.seg == 0) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) {
+                        const int k = wt.col(i, e);
+                        gsh[b][k] = (w == 0 ? 0.0 : gsh[b][k]) + wt.g64[b][i][e];
+                    }
+        }
+        __syncthreads();
+    }
+    double* part = p.partials + (int64_t)blk * NB * K1;
+    for (int b = 0; b < NB; ++b) {
+        for (int k = threadIdx.x; k < p.K; k += blockDim.x) {
+            double sacc = gsh[b][k];
+            if constexpr (DT == DT_FP8) sacc *= (double)p.scale[k];
+            part[b * K1 + 1 + k] = sacc;
+        }
+        if (threadIdx.x == 0) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int w = 0; w < WPB; ++w) sacc += fsh[w][b];
+            part[b * K1] = sacc;
+        }
+    }
+    merge_partials<WPB * 64, NB>(p, blk);
+}
+
 // ------------------------------------------------------------ plain kernel
 
 // Block blk (of p.nblocks) of the evaluation of f and g of p.nb (<= NB)
@@ -825,7 +874,6 @@ template <int DT, int LPR, int CPL, int R, int WPB, int NB>
 __device__ __forceinline__ void fg_pass(const FgParams& p, const int blk) {
     using WT = WaveTile<DT, LPR, CPL, R, NB>;
     constexpr int BATCH = WT::BATCH;
-    constexpr int KT = WT::KT;
     constexpr int VE = WT::VE;
 
     WT wt;
@@ -879,43 +927,7 @@ __device__ __forceinline__ void fg_pass(const FgParams& p, const int blk) {
         wt.stream_rows(p.X, p.y, r0, r1, rbuf[wave], nact);
     }
     wt.wave_totals();
-
-    // ---- block merge: waves add their slices into one LDS vector in order ----
-    const int K1 = p.K + 1;
-    __shared__ double gsh[NB][KT];
-    __shared__ double fsh[WPB][NB];
-    if (wt.lane == 0)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) fsh[wave][b] = wt.facc[b];
-    for (int w = 0; w < WPB; ++w) {
-        if (wave == w && wt.seg == 0) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int i = 0; i < CPL; ++i)
-#pragma unroll
-                    for (int e = 0; e < VE; ++e) {
-                        const int k = wt.col(i, e);
-                        gsh[b][k] = (w == 0 ? 0.0 : gsh[b][k]) + wt.g64[b][i][e];
-                    }
-        }
-        __syncthreads();
-    }
-    double* part = p.partials + (int64_t)blk * NB * K1;
-    for (int b = 0; b < NB; ++b) {
-        for (int k = threadIdx.x; k < p.K; k += blockDim.x) {
-            double sacc = gsh[b][k];
-            if constexpr (DT == DT_FP8) sacc *= (double)p.scale[k];
-            part[b * K1 + 1 + k] = sacc;
-        }
-        if (threadIdx.x == 0) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int w = 0; w < WPB; ++w) sacc += fsh[w][b];
-            part[b * K1] = sacc;
-        }
-    }
-    merge_partials<WPB * 64, NB>(p, blk);
+    block_merge<WT, DT, WPB, NB>(p, blk, wt, wave);
 }
 
 // f and g of p.nb (<= NB) coefficient vectors over all rows of one data set

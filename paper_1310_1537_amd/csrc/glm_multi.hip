@@ -2,6 +2,8 @@
 // data set per launch, and the fleet form that runs the passes of several
 // data sets of one geometry in one launch), and the public entry point
 // glm_logpost_grad_multi.
+#include <cstdlib>
+
 #include "fg_kernel.hpp"
 #include "runtime.hpp"
 
@@ -53,9 +55,22 @@ MultiInst mpick_nb(int lpr, int cpl, int nb) {
     return MultiInst{};
 }
 
+// GLM_MFMA=0 keeps BF16 passes on the VALU kernels (for comparisons).
+bool mx_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("GLM_MFMA");
+        return !e || std::atoi(e) != 0;
+    }();
+    return on;
+}
+
 }  // namespace
 
 MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max) {
+    if (dtype == GLM_BF16 && cpl == 1 && nb_max >= 4 && mx_enabled()) {
+        const MultiInst m = mx_instance(lpr);
+        if (m.fn) return m;
+    }
     for (int nb = 8; nb >= 2; nb /= 2) {
         if (nb > nb_max) continue;
         MultiInst m;
@@ -70,10 +85,10 @@ MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max) {
     return MultiInst{};
 }
 
-glm_status launch_fleet(const void* fn, int nblocks, const glmk::FleetJob* jobs,
+glm_status launch_fleet(const void* fn, int nblocks, int wpb, const glmk::FleetJob* jobs,
                         const uint16_t* blk_job, hipStream_t stream) {
     void* args[] = {&jobs, &blk_job};
-    GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(nblocks), dim3(WPB * 64), args, 0, stream));
+    GLM_HIP_CHECK(hipLaunchKernel(fn, dim3(nblocks), dim3(wpb * 64), args, 0, stream));
     return GLM_OK;
 }
 
@@ -100,6 +115,8 @@ glm_status glm_logpost_grad_multi(glm_ctx* ctx, glm_dataset_id id, const double*
     MultiInst mi = multi_instance(ds.d.dtype, ds.plan.lpr, ds.plan.cpl, nb);
     int NB = mi.fn ? mi.NB : 1;
     const void* fn = mi.fn ? mi.fn : ds.plan.fn;
+    Plan plan = ds.plan;
+    if (mi.fn) plan.wpb = mi.wpb;
     size_t np, ng, nc;
     scratch_need(ds.plan, K, NB, &np, &ng, &nc);
     Scratch* s = nullptr;
@@ -108,7 +125,7 @@ glm_status glm_logpost_grad_multi(glm_ctx* ctx, glm_dataset_id id, const double*
     // passes of NB vectors (the last one possibly partial)
     for (int b0 = 0; b0 < nb; b0 += NB) {
         const int n = std::min(NB, nb - b0);
-        st = launch_fused(ds.d, ds.plan, fn, NB, betas + (int64_t)b0 * K,
+        st = launch_fused(ds.d, plan, fn, NB, betas + (int64_t)b0 * K,
                           prior->mean ? prior->mean + (int64_t)b0 * K : nullptr, nullptr, prior->prec,
                           n, out + (int64_t)b0 * (K + 1), s, (hipStream_t)stream);
         if (st != GLM_OK) return st;

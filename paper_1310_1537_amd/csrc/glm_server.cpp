@@ -398,13 +398,14 @@ bool dispatch(glm_server* s) {
         ok = hipMemcpyAsync(sl->d_in, h, in_bytes, hipMemcpyHostToDevice, sl->stream) == hipSuccess;
         if (ok) {
             if (use_fleet) {
-                ok = launch_fleet(d0.mi.fleet, grid, (const glmk::FleetJob*)sl->d_in,
+                ok = launch_fleet(d0.mi.fleet, grid, d0.mi.wpb, (const glmk::FleetJob*)sl->d_in,
                                   (const uint16_t*)(sl->d_in + (size_t)nj * sizeof(glmk::FleetJob)),
                                   sl->stream) == GLM_OK;
             } else {
                 const void* fn = d0.mi.fn ? d0.mi.fn : d0.plan.fn;
+                const int wpb = d0.mi.fn ? d0.mi.wpb : d0.plan.wpb;
                 void* args[] = {&prm[0]};
-                ok = hipLaunchKernel(fn, dim3(d0.plan.nblocks), dim3(d0.plan.wpb * 64), args, 0,
+                ok = hipLaunchKernel(fn, dim3(d0.plan.nblocks), dim3(wpb * 64), args, 0,
                                      sl->stream) == hipSuccess;
             }
         }

@@ -145,8 +145,13 @@ struct MultiInst {
     int R = 0;
     int NB = 0;
     const void* fleet = nullptr;   // the same geometry over several data sets per launch
+    int wpb = 4;                   // waves per block of both forms
 };
 MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max);
+
+// The matrix-core instance for BF16 rows of lpr lanes (4 vectors per pass),
+// fn == nullptr where none is built.
+MultiInst mx_instance(int lpr);
 
 }  // namespace glmrt
 namespace glmk {
@@ -166,7 +171,7 @@ void fused_params(const glm_dataset_desc& d, const Plan& pl, int NB, const doubl
 // blk_job (one job index per block) in device memory; every job's parameters
 // are those launch_fused would pass for its data set, with blk0 its first
 // block.
-glm_status launch_fleet(const void* fn, int nblocks, const glmk::FleetJob* jobs,
+glm_status launch_fleet(const void* fn, int nblocks, int wpb, const glmk::FleetJob* jobs,
                         const uint16_t* blk_job, hipStream_t stream);
 
 // Launches a fused kernel instance (NB slots) for nb coefficient vectors

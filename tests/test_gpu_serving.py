@@ -318,6 +318,72 @@ def test_multi_ragged_k(ctx, K):
     glm.glm_dataset_unregister(ctx, ds)
 
 
+@pytest.mark.parametrize("K", [20, 72, 100, 128, 200, 260, 512])
+@pytest.mark.parametrize("nb", [2, 4, 7])
+def test_multi_bf16_matrix_core(ctx, K, nb):
+    """BF16 storage with 9 to 64 chunks per row (K from 65 to 512): passes of
+    four vectors run the matrix-core kernel (K = 20 the VALU one).  Rows
+    padded with NaN codes past column K (ragged K), N not a multiple of the
+    16-row batch, partly filled passes; every vector against the oracle on
+    the stored codes."""
+    X, y, bt = _data(10_007, K, 100 + K + nb)
+    Q = oracle.quantize_bf16(X)
+    ld = (K + 7) // 8 * 8 + 8
+    buf = np.full((X.shape[0], ld), 0x7FC0, np.uint16)
+    buf[:, :K] = Q
+    Qd = to_dev(buf)[:, :K]
+    yd = to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
+    B = _betas(bt, nb, K + 3 * nb)
+    out = torch.full((nb, K + 1), float("nan"), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), nb, glm.make_prior(0.01), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    Xd = oracle.decode_bf16(Q)
+    for b in range(nb):
+        _check(o[b, 0], o[b, 1:], Xd, y, B[b], 0.01, Xo=Q, okw={"dtype": "bf16"})
+    # slot 0 does not depend on what the other slots of its pass hold
+    B2 = B.copy()
+    B2[1:] = _betas(bt, nb - 1, K + 3 * nb + 1)
+    out2 = torch.empty((nb, K + 1), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B2), nb, glm.make_prior(0.01), out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(o[0], out2.cpu().numpy()[0])
+    glm.glm_dataset_unregister(ctx, ds)
+
+
+def test_multi_bf16_matrix_core_edges(ctx):
+    """Empty data set (prior only), fewer rows than one batch, and non-finite
+    beta (NaN out) through the matrix-core kernel."""
+    K = 96
+    X, y, bt = _data(7, K, 5)
+    Q = oracle.quantize_bf16(X)
+    B = _betas(bt, 4, 6)
+    for n in (0, 7):
+        Qd, yd = to_dev(Q[:n].reshape(n, K)), to_dev(y[:n])
+        ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
+        out = torch.empty((4, K + 1), dtype=torch.float64, device=DEV)
+        glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), 4, glm.make_prior(0.01), out)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        for b in range(4):
+            _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q[:n].reshape(n, K)), y[:n], B[b], 0.01,
+                   Xo=Q[:n].reshape(n, K), okw={"dtype": "bf16"})
+        glm.glm_dataset_unregister(ctx, ds)
+    Qd, yd = to_dev(Q), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
+    Bn = B.copy()
+    Bn[2, 3] = np.nan
+    out = torch.empty((4, K + 1), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(Bn), 4, glm.make_prior(0.01), out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.isnan(o[2, 0])
+    for b in (0, 1, 3):
+        _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 0.01, Xo=Q, okw={"dtype": "bf16"})
+    glm.glm_dataset_unregister(ctx, ds)
+
+
 @pytest.mark.timeout(900)
 def test_serving_workload_full_configuration(ctx):
     """The 64 data sets of the serving workload (N log-uniform on [1e3, 2e6],
