@@ -178,8 +178,12 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
             __threadfence();   // acquire side: tiles published by other blocks
         }
         __syncthreads();
+        // The won groups are spread over the waves (entry j to wave
+        // j mod WPB); a wave adds a group's tile partials per column in tile
+        // order and its prior term with a butterfly, so groups need no block
+        // barrier of their own.
         const int nq = min(NT, q1 - qb);
-        for (int j = 0; j < nq; ++j) {
+        for (int j = wave; j < nq; j += WPB) {
             if (!s_win[j]) continue;
             const int g = p.block_groups[qb + j];
             const int t0 = p.tile_first[g];
@@ -188,29 +192,23 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
             const double* m =
                 p.mean ? (p.mean_per_group ? p.mean + (int64_t)g * K : p.mean) : nullptr;
             double* o = p.out + (int64_t)g * K1;
-            double pf = 0.0;
-            for (int k = threadIdx.x; k < K1; k += NT) {
+            double pf = 0.0, flik = 0.0;
+            for (int k = wt.lane; k < K1; k += 64) {
                 const double sacc = ordered_sum(p.partials + (int64_t)t0 * K1 + k, nt, K1);
                 if (k == 0) {
-                    o[0] = sacc;
+                    flik = sacc;
                 } else {
                     const double d = beta[k - 1] - (m ? m[k - 1] : 0.0);
                     pf += d * d;
                     o[k] = sacc - p.prec * d;
                 }
             }
-            __shared__ double s_pf[NT];
-            s_pf[threadIdx.x] = pf;
-            __syncthreads();
-            for (int w = NT / 2; w > 0; w >>= 1) {
-                if ((int)threadIdx.x < w) s_pf[threadIdx.x] += s_pf[threadIdx.x + w];
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                o[0] = o[0] - 0.5 * p.prec * s_pf[0];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) pf += __shfl_xor(pf, d, 64);
+            if (wt.lane == 0) {
+                o[0] = flik - 0.5 * p.prec * pf;
                 __hip_atomic_store(&p.counters[g], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            __syncthreads();
         }
         __syncthreads();
     }
