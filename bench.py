@@ -882,11 +882,128 @@ def bench_hessian(args):
     }
 
 
+def bench_multi(args):
+    """Several coefficient vectors per pass (glm_logpost_grad_multi) over about
+    2 GB of X for every storage type and row width of the serving workload:
+    microseconds per launch and per vector at 1, 2, 4 and 8 vectors; for BF16
+    rows of 65 columns and more at 4 and 8 vectors, the matrix-core form beside
+    the VALU one (GLM_MFMA=0).  X ~ N(0, 1) drawn on the device (BF16 codes
+    by the library's encoder), y ~ Bernoulli(1/2), beta ~ N(0, 0.01^2 I).
+    The headline value is vector evaluations per second of the BF16 K = 512
+    pass of four vectors on the matrix cores."""
+
+    import numpy as np
+    import torch
+
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    ctx = glm.glm_create(0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20131006)
+    stream = torch.cuda.current_stream()
+    reps = max(3, min(args.steps, 20))
+    rows, keep = [], None
+
+    def timed(ds, K, nb):
+        B = (0.01 * torch.randn((nb, K), device=dev, dtype=torch.float64, generator=gen)).contiguous()
+        out = torch.empty((nb, K + 1), device=dev, dtype=torch.float64)
+        pr = glm.make_prior(0.01)
+        for _ in range(3):
+            glm.glm_logpost_grad_multi(ctx, ds, B, nb, pr, out, stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            glm.glm_logpost_grad_multi(ctx, ds, B, nb, pr, out, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e3 / reps
+
+    t0 = time.perf_counter()
+    try:
+        for K in (8, 32, 128, 512):
+            for dt in ("f32", "bf16"):
+                es = 4 if dt == "f32" else 2
+                N = int(2.0e9 // (K * es))
+                X = torch.randn((N, K), device=dev, dtype=torch.float32, generator=gen)
+                y = (torch.rand(N, device=dev, generator=gen) < 0.5).to(torch.uint8)
+                code = glm.GLM_F32
+                if dt == "bf16":
+                    Q = torch.empty((N, K), dtype=torch.uint16, device=dev)
+                    glm.glm_quantize_bf16(ctx, X, Q)
+                    torch.cuda.synchronize()
+                    del X
+                    X, code = Q, glm.GLM_BF16
+                ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y, dtype=code))
+                nbytes = N * (K * es + 1)
+                for nb in (1, 2, 4, 8):
+                    forms = [("vector ALU", "0"), ("matrix cores", "1")] \
+                        if dt == "bf16" and K >= 65 and nb >= 4 else [("vector ALU", None)]
+                    for form, env in forms:
+                        if env is not None:
+                            os.environ["GLM_MFMA"] = env
+                        us = timed(ds, K, nb)
+                        rows.append({"K": K, "storage": dt, "nb": nb, "form": form, "N": N,
+                                     "us_per_launch": us, "us_per_vector": us / nb,
+                                     "GBps_x_once": nbytes / us / 1e3})
+                        if dt == "bf16" and K == 512 and nb == 4 and env == "1":
+                            keep = rows[-1]
+                os.environ.pop("GLM_MFMA", None)
+                glm.glm_dataset_unregister(ctx, ds)
+                del X, y
+                torch.cuda.empty_cache()
+    finally:
+        os.environ.pop("GLM_MFMA", None)
+        glm.glm_destroy(ctx)
+    wall = time.perf_counter() - t0
+    for r in rows:
+        print("[multi] K=%4d %-4s nb=%d %-12s %9.1f us/launch %8.1f us/vector %6.0f GB/s (X once)"
+              % (r["K"], r["storage"], r["nb"], r["form"], r["us_per_launch"], r["us_per_vector"],
+                 r["GBps_x_once"]), file=sys.stderr, flush=True)
+    result = {
+        "metric": "several-beta passes: vector evals/s (fused f+g per vector, FP64 results)",
+        "value": 4.0 / (keep["us_per_launch"] * 1e-6), "unit": "vector evals/s",
+        "n_gpus": 1, "steps": reps, "warmup": 3, "ms_per_step": keep["us_per_launch"] / 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "several beta per pass: about 2 GB of X per storage type and K in "
+                               "{8, 32, 128, 512}; headline BF16 K=512, 4 vectors, matrix cores",
+                   "N": keep["N"], "K": 512},
+        "roofline": {"bound": "hbm", "achieved": keep["GBps_x_once"], "peak": 8000.0, "unit": "GB/s",
+                     "frac": keep["GBps_x_once"] / 8000.0, "traffic": None,
+                     "kernel": "fg_fused_mx<64, 4, 4>",
+                     "note": "X bytes read once per pass of four vectors over the mean launch time; "
+                             "the kernel is bound by its per-row map, LDS and VALU latency"},
+        "table": rows, "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        g = np.random.default_rng(20131006)
+        n_s, K = 20_000, 512
+        Xs = g.standard_normal((n_s, K)).astype(np.float32)
+        Qs = oracle.quantize_bf16(Xs)
+        ys = (g.random(n_s) < 0.5).astype(np.uint8)
+        Bs = 0.01 * g.standard_normal((4, K))
+        c0 = time.perf_counter()
+        reps_c = 0
+        while time.perf_counter() - c0 < 10.0:
+            oracle.logpost_grad_multi(Qs, ys, Bs, 0.01, dtype="bf16")
+            reps_c += 1
+        dt_c = time.perf_counter() - c0
+        result["cpu_baseline"] = {
+            "value": 4 * reps_c / dt_c * n_s / keep["N"], "unit": "vector evals/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "4 vectors over a 20,000-row BF16 K=512 sample, repeated for about 10 s and "
+                      "scaled to the benchmark's N (single-threaded FP64 C)"}
+    return result
+
+
 WORKLOADS = {"copy": bench_copy, "plain_big": bench_plain_big, "precision": bench_precision,
              "batched": bench_batched, "plain_small": bench_plain_small,
              "serving": bench_serving, "diff": bench_diff,
              "poisson": lambda a: bench_plain_big(a, poisson=True),
-             "sampler": bench_sampler, "hessian": bench_hessian}
+             "sampler": bench_sampler, "hessian": bench_hessian, "multi": bench_multi}
 
 
 def main() -> int:

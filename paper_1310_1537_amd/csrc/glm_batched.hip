@@ -273,7 +273,7 @@ glm_status autotune(glm_groupset* gs) {
     int64_t bestT = 0;
     int bestB = 1;
     glm_status st = GLM_OK;
-    for (int mult : {2, 4, 8, 16, 32, 64}) {
+    for (int mult : {2, 4, 8, 12, 16, 24, 32, 48, 64}) {
         for (int bpc : {1, 2}) {
             const int64_t T = (int64_t)gs->batch_rows * mult;
             st = apply_schedule(gs, T, bpc);

@@ -55,13 +55,11 @@ MultiInst mpick_nb(int lpr, int cpl, int nb) {
     return MultiInst{};
 }
 
-// GLM_MFMA=0 keeps BF16 passes on the VALU kernels (for comparisons).
+// GLM_MFMA=0 keeps BF16 passes on the VALU kernels (for comparisons); read
+// at every choice of instance, so a process can time both forms.
 bool mx_enabled() {
-    static const bool on = [] {
-        const char* e = std::getenv("GLM_MFMA");
-        return !e || std::atoi(e) != 0;
-    }();
-    return on;
+    const char* e = std::getenv("GLM_MFMA");
+    return !e || std::atoi(e) != 0;
 }
 
 }  // namespace
