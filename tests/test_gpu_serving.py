@@ -292,6 +292,34 @@ def test_server_fleet_launch_bitwise_and_oracle(ctx):
             _check(f, g, Xh, y, beta, 0.01, Xo=Q, okw={"dtype": "bf16"})
 
 
+@pytest.mark.parametrize("K", [128, 512])
+def test_server_fleet_matrix_core_bitwise_and_oracle(ctx, K):
+    """The matrix-core several-beta kernel in fleet launches: BF16 data sets of
+    one geometry (K = 128: 8 waves per block; K = 512: 4) with N from 0 to
+    60,000 give in a shared launch the bits of one launch per data set, and
+    match the oracle on the stored codes."""
+    Ns = [1_000, 0, 17, 60_000, 4_099]
+    sets, host = [], []
+    for i, N in enumerate(Ns):
+        X, y, bt = _data(N, K, 400 + K + i)
+        Q = oracle.quantize_bf16(X)
+        sets.append((to_dev(Q), to_dev(y), glm.GLM_BF16))
+        host.append((oracle.decode_bf16(Q), y, bt, Q))
+    rng = np.random.default_rng(410 + K)
+    reqs = []
+    for r in range(40):
+        i = int(rng.integers(0, len(sets)))
+        reqs.append((i, np.ascontiguousarray(host[i][2] + 0.1 * rng.standard_normal(K))))
+    fleet, st = _fleet_run(ctx, sets, reqs, 0)
+    single, st1 = _fleet_run(ctx, sets, reqs, 1)
+    assert st["launches"] < st["passes"], st
+    assert st1["launches"] == st1["passes"]
+    for (i, beta), (f, g), (f1, g1) in zip(reqs, fleet, single):
+        assert f == f1 and np.array_equal(g, g1), i
+        Xh, y, _, Q = host[i]
+        _check(f, g, Xh, y, beta, 0.01, Xo=Q, okw={"dtype": "bf16"})
+
+
 def test_server_max_sets_argument(ctx):
     for bad in (-1, 257):
         with pytest.raises(glm.GlmError) as e:
