@@ -191,7 +191,9 @@ glm_status glm_logpost_grad_multi(glm_ctx* ctx, glm_dataset_id id, const double*
                                   int32_t nb, const glm_prior* prior, double* out, void* stream);
 
 /* Host-buffer form mirroring the paper's routine: copies beta (and the
- * prior mean, if any) to the device, launches, copies f and g back and waits.
+ * prior mean, if any) to the device, launches and waits; the kernel writes f
+ * and g straight into the context's coherent pinned staging memory, from
+ * which they are copied to f and g_host (no device-to-host copy).
  *   beta_host  K doubles;  prior->mean host K doubles or NULL
  *   f          host double;  g_host  host K doubles (may be NULL)
  * Uses the context's own stream.  Same errors as glm_logpost_grad. */

@@ -203,7 +203,8 @@ glm_status glm_logpost_grad_host(glm_ctx* ctx, glm_dataset_id id, const double* 
         ctx->h_stage = nullptr;
         ctx->d_stage = nullptr;
         ctx->stage_cap = 0;
-        GLM_HIP_CHECK(hipHostMalloc((void**)&ctx->h_stage, need * sizeof(double)));
+        // coherent: the kernel writes f and g straight into it (no copy back)
+        GLM_HIP_CHECK(hipHostMalloc((void**)&ctx->h_stage, need * sizeof(double), hipHostMallocCoherent));
         GLM_HIP_CHECK(hipMalloc((void**)&ctx->d_stage, need * sizeof(double)));
         ctx->stage_cap = need;
     }
@@ -219,10 +220,8 @@ glm_status glm_logpost_grad_host(glm_ctx* ctx, glm_dataset_id id, const double* 
     }
     hipStream_t s = ctx->own_stream;
     GLM_HIP_CHECK(hipMemcpyAsync(db, hb, nin * sizeof(double), hipMemcpyHostToDevice, s));
-    st = launch_plain(ctx, it->second, db, &pd, db + 2 * K, s);
+    st = launch_plain(ctx, it->second, db, &pd, hb + 2 * K, s);
     if (st != GLM_OK) return st;
-    GLM_HIP_CHECK(hipMemcpyAsync(hb + 2 * K, db + 2 * K, (K + 1) * sizeof(double),
-                                 hipMemcpyDeviceToHost, s));
     GLM_HIP_CHECK(hipStreamSynchronize(s));
     *f = hb[2 * K];
     if (g_host) std::memcpy(g_host, hb + 2 * K + 1, K * sizeof(double));
