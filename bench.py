@@ -971,7 +971,8 @@ def bench_multi(args):
                                "{8, 32, 128, 512}; headline BF16 K=512, 4 vectors, matrix cores",
                    "N": keep["N"], "K": 512},
         "roofline": {"bound": "hbm", "achieved": keep["GBps_x_once"], "peak": 8000.0, "unit": "GB/s",
-                     "frac": keep["GBps_x_once"] / 8000.0, "traffic": None,
+                     "frac": keep["GBps_x_once"] / 8000.0,
+                     "traffic": measured_traffic("fg_fused_mx_several_beta", "mx"),
                      "kernel": "fg_fused_mx<64, 4, 4>",
                      "note": "X bytes read once per pass of four vectors over the mean launch time; "
                              "the kernel is bound by its per-row map, LDS and VALU latency"},

@@ -31,6 +31,7 @@ KERNEL_SOURCES = {
     "plain": ("tr_math.hpp", "fg_kernel.hpp", "glm_plain.hip"),
     "batched": ("tr_math.hpp", "fg_kernel.hpp", "fg_batched.hpp", "glm_batched.hip"),
     "diff": ("tr_math.hpp", "elem.hpp", "glm_diff.hip"),
+    "mx": ("tr_math.hpp", "fg_kernel.hpp", "fg_mfma.hpp", "glm_multi_mx.hip"),
 }
 
 
