@@ -346,7 +346,7 @@ def test_multi_ragged_k(ctx, K):
     glm.glm_dataset_unregister(ctx, ds)
 
 
-@pytest.mark.parametrize("K", [20, 72, 100, 128, 200, 260, 512])
+@pytest.mark.parametrize("K", [20, 65, 72, 100, 128, 200, 257, 260, 512])
 @pytest.mark.parametrize("nb", [2, 4, 7])
 def test_multi_bf16_matrix_core(ctx, K, nb):
     """BF16 storage with 9 to 64 chunks per row (K from 65 to 512): passes of
