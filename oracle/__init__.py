@@ -16,8 +16,10 @@ gradient, a Gaussian prior N(m, prec^-1 I)):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -109,6 +111,42 @@ def logpost_grad(X, y, beta, prec, mean=None, dtype=None, scale=None, family="lo
     if rc:
         raise ValueError("oracle rejected its arguments")
     return out[0], out[1:].copy()
+
+
+def row_blocks(N: int, parts: int):
+    """[a, b) row ranges splitting N rows into at most `parts` blocks."""
+    b = np.linspace(0, N, max(1, parts) + 1).astype(np.int64)
+    return [(int(b[i]), int(b[i + 1])) for i in range(len(b) - 1) if b[i + 1] > b[i]]
+
+
+def logpost_grad_blocks(X, y, beta, prec, mean=None, threads=None, dtype=None, scale=None,
+                        family="logistic", pool=None):
+    """logpost_grad over row blocks in host threads (the C code releases the
+    interpreter lock).  Each block is evaluated with the prior left out, the
+    block values are added in block order with math.fsum (per component of
+    g too) and the prior is added once: the likelihood is a sum over rows, so
+    this is the same quantity (row-split additivity, pinned by the oracle
+    tests).  Returns (f, g)."""
+    X = np.asarray(X)
+    N, K = X.shape
+    threads = threads or max(1, min(16, os.cpu_count() or 1))
+    blocks = row_blocks(N, 4 * threads)
+
+    def one(ab):
+        a, b = ab
+        return logpost_grad(X[a:b], y[a:b], beta, 0.0, None, dtype, scale, family)
+
+    if pool is None:
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(one, blocks))
+    else:
+        parts = list(pool.map(one, blocks))
+    beta = np.asarray(beta, np.float64)
+    d = beta - (0.0 if mean is None else np.asarray(mean, np.float64))
+    f = math.fsum([p[0] for p in parts]) - 0.5 * prec * math.fsum(d * d)
+    G = np.array([p[1] for p in parts]).reshape(len(parts), K)
+    g = np.array([math.fsum(G[:, k]) for k in range(K)]) - prec * d
+    return f, g
 
 
 def linpred(X, beta, dtype=None, scale=None):

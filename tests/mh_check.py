@@ -115,7 +115,7 @@ class Formats:
 
         from paper_1310_1537_amd import glm
         t0 = time.perf_counter()
-        w = synth.plain_big(N, K, 1, np.float32, workload_index=2)
+        w = synth.plain_big(N, K, 1000, np.float32, workload_index=2)
         log(f"[mh] generated N={N} K={K} in {time.perf_counter() - t0:.1f} s")
         t0 = time.perf_counter()
         Qb = quantize_rows(pool, w.X, "bf16")

@@ -1,7 +1,5 @@
 """GPU parity of the batched hierarchical-model evaluation
 (glm_logpost_grad_batched) against the FP64 oracle's per-group results."""
-import math
-
 import numpy as np
 import pytest
 
@@ -10,10 +8,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
+import parity_bounds as pb  # noqa: E402
+import sweeps  # noqa: E402
 import synth  # noqa: E402
 
 if torch.cuda.is_available():
-    from gpu_helpers import DEV, Ctx, bounds, eval_gpu, to_dev  # noqa: E402
+    from gpu_helpers import DEV, Ctx, check_against_oracle, eval_gpu, to_dev  # noqa: E402
     from paper_1310_1537_amd import glm  # noqa: E402
 
 
@@ -24,28 +24,22 @@ def ctx():
     c.close()
 
 
-def _groups(sizes, K, seed, dtype=np.float32):
-    g = np.random.default_rng(seed)
-    off = np.zeros(len(sizes) + 1, np.int64)
-    off[1:] = np.cumsum(sizes)
-    X = g.standard_normal((int(off[-1]), K)).astype(dtype)
-    B = g.standard_normal((len(sizes), K)) / math.sqrt(K)
-    y = (g.random(int(off[-1])) < 0.5).astype(np.uint8)
-    return X, y, off, B
+_groups = sweeps.groups
 
 
 def _run(ctx, X, y, off, B, prec, mean=None, per_group=False, tune=False, dtype=None, scale=None,
-         repeat=1):
+         repeat=1, zero_leg=False):
+    """Batched results (repeat calls); with zero_leg, one more call at
+    beta = 0 for every group is appended."""
     Xd, yd = to_dev(X), to_dev(y)
     desc = glm.make_desc(Xd, yd, dtype=dtype, col_scale=scale)
     gs = glm.glm_groupset_create(ctx, desc, off, tune=tune)
     G, K = B.shape
-    Bd = to_dev(B)
     md = None if mean is None else to_dev(mean)
     out = torch.full((G, K + 1), float("nan"), dtype=torch.float64, device=DEV)
     res = []
-    for _ in range(repeat):
-        glm.glm_logpost_grad_batched(ctx, gs, Bd, glm.make_prior(prec, md, per_group), out)
+    for Bc in [B] * repeat + ([np.zeros_like(B)] if zero_leg else []):
+        glm.glm_logpost_grad_batched(ctx, gs, to_dev(Bc), glm.make_prior(prec, md, per_group), out)
         torch.cuda.synchronize()
         res.append(out.cpu().numpy().copy())
     info = glm.glm_groupset_query(gs)
@@ -60,10 +54,14 @@ def _check_groups(got, Xd64, y, off, B, prec, mean=None, storage="f32", X_oracle
     for g in range(len(off) - 1):
         a, b = off[g], off[g + 1]
         mg = None if mean is None else (mean[g] if mean.ndim == 2 else mean)
-        bf, bg = bounds(Xd64[a:b], y[a:b], B[g], ref[g, 0], ref[g, 1:], storage)
-        assert abs(got[g, 0] - ref[g, 0]) <= bf + 1e-12 * abs(ref[g, 0]), (g, got[g, 0], ref[g, 0])
-        assert np.all(np.abs(got[g, 1:] - ref[g, 1:]) <= bg + 1e-12), g
-        del mg
+        pb.check(got[g, 0], got[g, 1:], Xd64[a:b], y[a:b], B[g], prec, mg, storage,
+                 okw.get("family", "logistic"), ref=(ref[g, 0], ref[g, 1:]))
+
+
+def _check_both(res, Xd64, y, off, B, prec, **kw):
+    """res = [at B, at 0] from _run(..., zero_leg=True)."""
+    _check_groups(res[0], Xd64, y, off, B, prec, **kw)
+    _check_groups(res[1], Xd64, y, off, np.zeros_like(B), prec, **kw)
 
 
 SIZES = [0, 1, 63, 64, 65, 127, 128, 129, 1000, 1025, 5000, 20, 0, 3, 2049, 700]
@@ -73,18 +71,18 @@ SIZES = [0, 1, 63, 64, 65, 127, 128, 129, 1000, 1025, 5000, 20, 0, 3, 2049, 700]
 def test_ragged_groups_f32(ctx, tune):
     X, y, off, B = _groups(SIZES, 32, 1)
     mu = np.linspace(-0.3, 0.3, 32)
-    (got,), info = _run(ctx, X, y, off, B, 4.0, mean=mu, tune=tune)
+    res, info = _run(ctx, X, y, off, B, 4.0, mean=mu, tune=tune, zero_leg=True)
     assert info["items"] >= len(SIZES)
-    _check_groups(got, X.astype(np.float64), y, off, B, 4.0, mean=mu)
+    _check_both(res, X.astype(np.float64), y, off, B, 4.0, mean=mu)
 
 
 def test_split_groups_are_merged(ctx):
     """Default tile length is 8 batches (1024 rows at K=32): the 5000- and
     2049-row groups are split and merged in-kernel."""
     X, y, off, B = _groups(SIZES, 32, 2)
-    (got,), info = _run(ctx, X, y, off, B, 0.5)
+    res, info = _run(ctx, X, y, off, B, 0.5, zero_leg=True)
     assert info["split_tiles"] >= 2
-    _check_groups(got, X.astype(np.float64), y, off, B, 0.5)
+    _check_both(res, X.astype(np.float64), y, off, B, 0.5)
 
 
 def test_per_group_prior_mean(ctx):
@@ -97,22 +95,23 @@ def test_per_group_prior_mean(ctx):
 @pytest.mark.parametrize("K", [4, 8, 16, 64, 128, 256])
 def test_widths_and_f64(ctx, K):
     X, y, off, B = _groups([50, 0, 3000, 700, 1], K, 5 + K)
-    (got,), _ = _run(ctx, X, y, off, B, 0.1)
-    _check_groups(got, X.astype(np.float64), y, off, B, 0.1)
+    res, _ = _run(ctx, X, y, off, B, 0.1, zero_leg=True)
+    _check_both(res, X.astype(np.float64), y, off, B, 0.1)
     X64 = X.astype(np.float64)
-    (got64,), _ = _run(ctx, X64, y, off, B, 0.1)
-    _check_groups(got64, X64, y, off, B, 0.1, storage="f64")
+    res64, _ = _run(ctx, X64, y, off, B, 0.1, zero_leg=True)
+    _check_both(res64, X64, y, off, B, 0.1, storage="f64")
 
 
 def test_bf16_and_fp8_groups(ctx):
     X, y, off, B = _groups(SIZES, 64, 6)
     Qb = oracle.quantize_bf16(X)
-    (got,), _ = _run(ctx, Qb, y, off, B, 1.0, dtype=glm.GLM_BF16)
-    _check_groups(got, oracle.decode_bf16(Qb), y, off, B, 1.0, X_oracle=Qb, okw={"dtype": "bf16"})
+    res, _ = _run(ctx, Qb, y, off, B, 1.0, dtype=glm.GLM_BF16, zero_leg=True)
+    _check_both(res, oracle.decode_bf16(Qb), y, off, B, 1.0, storage="bf16", X_oracle=Qb,
+                okw={"dtype": "bf16"})
     Q8, s = oracle.quantize_fp8(X)
-    (got,), _ = _run(ctx, Q8, y, off, B, 1.0, dtype=glm.GLM_FP8_E4M3, scale=to_dev(s))
-    _check_groups(got, oracle.decode_fp8(Q8, s), y, off, B, 1.0, X_oracle=Q8,
-                  okw={"dtype": "fp8", "scale": s})
+    res, _ = _run(ctx, Q8, y, off, B, 1.0, dtype=glm.GLM_FP8_E4M3, scale=to_dev(s), zero_leg=True)
+    _check_both(res, oracle.decode_fp8(Q8, s), y, off, B, 1.0, storage="fp8", X_oracle=Q8,
+                okw={"dtype": "fp8", "scale": s})
 
 
 def test_repeated_calls_are_bitwise_identical(ctx):
@@ -130,9 +129,10 @@ def test_group_result_matches_plain_call(ctx):
     for g in (2, 10, 14):
         a, b = off[g], off[g + 1]
         f, gg = eval_gpu(ctx, to_dev(X[a:b]), to_dev(y[a:b]), B[g], 4.0)
-        bf, bg = bounds(X[a:b].astype(np.float64), y[a:b], B[g], f, gg)
-        assert abs(f - got[g, 0]) <= 2 * bf
-        assert np.all(np.abs(gg - got[g, 1:]) <= 2 * bg)
+        bd = pb.error_bounds(X[a:b].astype(np.float64), y[a:b], B[g], 4.0)
+        assert abs(f - got[g, 0]) <= 2 * min(bd["f_worst"], bd["f_prob"])
+        assert np.all(np.abs(gg - got[g, 1:]) <= 2 * np.minimum(bd["g_worst"], bd["g_prob"]))
+        check_against_oracle(f, gg, X[a:b].astype(np.float64), y[a:b], B[g], 4.0)
 
 
 def test_invalid_offsets(ctx):
@@ -149,9 +149,10 @@ def test_hierarchical_workload_full_size(ctx):
     [20, 50,000], K = 32, FP32; autotuned schedule; every group within its
     derived bound of the oracle."""
     w = synth.hierarchical()
-    (got,), info = _run(ctx, w.X, w.y, w.offsets, w.betas, w.prec, mean=w.mu, tune=True)
+    res, info = _run(ctx, w.X, w.y, w.offsets, w.betas, w.prec, mean=w.mu, tune=True,
+                     zero_leg=True)
     print("hierarchical schedule:", info, flush=True)
-    _check_groups(got, w.X.astype(np.float64), w.y, w.offsets, w.betas, w.prec, mean=w.mu)
+    _check_both(res, w.X.astype(np.float64), w.y, w.offsets, w.betas, w.prec, mean=w.mu)
 
 
 @pytest.mark.parametrize("K", [3, 13, 37])

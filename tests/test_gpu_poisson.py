@@ -11,10 +11,13 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
+import parity_bounds as pb  # noqa: E402
+import sweeps  # noqa: E402
 import synth  # noqa: E402
 
 if torch.cuda.is_available():
-    from gpu_helpers import DEV, Ctx, bounds, check_against_oracle, eval_gpu, to_dev  # noqa: E402
+    from gpu_helpers import (DEV, Ctx, check_against_oracle, eval_gpu, sweep_point,  # noqa: E402
+                             to_dev)
     from paper_1310_1537_amd import glm  # noqa: E402
 
 POI = {"family": "poisson"}
@@ -27,23 +30,18 @@ def ctx():
     c.close()
 
 
-def _data(N, K, seed, dtype=np.float32):
-    g = np.random.default_rng(seed)
-    X = g.standard_normal((N, K)).astype(dtype)
-    bt = 0.5 * g.standard_normal(K) / math.sqrt(K)
-    y = np.minimum(g.poisson(np.exp(X.astype(np.float64) @ bt)), 255).astype(np.uint8)
-    return X, y, bt + 0.05 * g.standard_normal(K)
+_data = sweeps.poisson
 
 
-@pytest.mark.parametrize("K", [4, 13, 64, 256, 1000])
-@pytest.mark.parametrize("N", [1, 777, 40_009])
+@pytest.mark.parametrize("K", sweeps.POISSON_K)
+@pytest.mark.parametrize("N", sweeps.POISSON_N)
 def test_plain_f32(ctx, K, N):
     X, y, beta = _data(N, K, K + N)
     Xd, yd = to_dev(X), to_dev(y)
     if (K * 4) % 16:
         Xd = glm.aligned_rows(Xd)
-    f, g = eval_gpu(ctx, Xd, yd, beta, 0.01, family=glm.GLM_POISSON)
-    check_against_oracle(f, g, X.astype(np.float64), y, beta, 0.01, oracle_kw=POI)
+    sweep_point(ctx, Xd, yd, X.astype(np.float64), y, beta, 0.01, oracle_kw=POI,
+                family=glm.GLM_POISSON)
 
 
 @pytest.mark.parametrize("kind", ["f64", "bf16", "fp8"])
@@ -59,14 +57,14 @@ def test_plain_other_storage(ctx, kind):
         Q = oracle.quantize_bf16(X)
         f, g = eval_gpu(ctx, to_dev(Q), yd, beta, 0.5, m, dtype=glm.GLM_BF16,
                         family=glm.GLM_POISSON)
-        check_against_oracle(f, g, oracle.decode_bf16(Q), y, beta, 0.5, m, X_for_oracle=Q,
-                             oracle_kw={"dtype": "bf16", **POI})
+        check_against_oracle(f, g, oracle.decode_bf16(Q), y, beta, 0.5, m, storage="bf16",
+                             X_for_oracle=Q, oracle_kw={"dtype": "bf16", **POI})
     else:
         Q, s = oracle.quantize_fp8(X)
         f, g = eval_gpu(ctx, to_dev(Q), yd, beta, 0.5, m, dtype=glm.GLM_FP8_E4M3,
                         scale=to_dev(s), family=glm.GLM_POISSON)
-        check_against_oracle(f, g, oracle.decode_fp8(Q, s), y, beta, 0.5, m, X_for_oracle=Q,
-                             oracle_kw={"dtype": "fp8", "scale": s, **POI})
+        check_against_oracle(f, g, oracle.decode_fp8(Q, s), y, beta, 0.5, m, storage="fp8",
+                             X_for_oracle=Q, oracle_kw={"dtype": "fp8", "scale": s, **POI})
 
 
 def test_closed_form_at_zero(ctx):
@@ -74,8 +72,8 @@ def test_closed_form_at_zero(ctx):
     X, y, _ = _data(12_345, 32, 4)
     f, g = eval_gpu(ctx, to_dev(X), to_dev(y), np.zeros(32), 0.0, family=glm.GLM_POISSON)
     assert f == -12_345.0
-    want = X.astype(np.float64).T @ (y.astype(np.float64) - 1.0)
-    np.testing.assert_allclose(g, want, rtol=1e-6, atol=1e-3)
+    # g = X^t (y - 1): only the FP32 products and partial sums round
+    check_against_oracle(f, g, X.astype(np.float64), y, np.zeros(32), 0.0, oracle_kw=POI)
 
 
 def test_multi(ctx):
@@ -118,9 +116,8 @@ def test_batched_groups(ctx):
     X64 = X.astype(np.float64)
     for i in range(len(sizes)):
         a, b = off[i], off[i + 1]
-        bf, bg = bounds(X64[a:b], y[a:b], B[i], ref[i, 0], ref[i, 1:], "f32", "poisson")
-        assert abs(got[i, 0] - ref[i, 0]) <= bf + 1e-12 * abs(ref[i, 0]), i
-        assert np.all(np.abs(got[i, 1:] - ref[i, 1:]) <= bg + 1e-12), i
+        pb.check(got[i, 0], got[i, 1:], X64[a:b], y[a:b], B[i], 4.0, None, "f32", "poisson",
+                 ref=(ref[i, 0], ref[i, 1:]))
 
 
 def test_differential_update(ctx):
@@ -179,6 +176,6 @@ def test_poisson_workload_full_size(ctx):
     relative."""
     w = synth.plain_poisson(n_evals=1)
     f, g = eval_gpu(ctx, to_dev(w.X), to_dev(w.y), w.betas[0], w.prec, family=glm.GLM_POISSON)
-    fo, go = oracle.logpost_grad(w.X, w.y, w.betas[0], w.prec, family="poisson")
+    fo, go = oracle.logpost_grad_blocks(w.X, w.y, w.betas[0], w.prec, family="poisson")
     assert abs(f - fo) <= 1e-9 * abs(fo)
     assert np.linalg.norm(g - go) <= 1e-7 * np.linalg.norm(go)

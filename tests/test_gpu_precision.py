@@ -11,9 +11,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
+import sweeps  # noqa: E402
 
 if torch.cuda.is_available():
-    from gpu_helpers import DEV, Ctx, check_against_oracle, eval_gpu, to_dev  # noqa: E402
+    from gpu_helpers import DEV, Ctx, eval_gpu, sweep_point, to_dev  # noqa: E402
     from paper_1310_1537_amd import glm  # noqa: E402
 
 
@@ -24,15 +25,7 @@ def ctx():
     c.close()
 
 
-def _matrix(N, K, seed):
-    g = np.random.default_rng(seed)
-    X = g.standard_normal((N, K)).astype(np.float32)
-    X[:, -max(1, K // 10):] = (g.random((N, max(1, K // 10))) < 0.3)
-    X[0, 0] = 0.0
-    if N > 3 and K > 2:
-        X[1, 1] = 1e-30          # below every FP8 step after scaling
-        X[2, 2] = -7.25e-3
-    return X
+_matrix = sweeps.precision_matrix
 
 
 def test_bf16_encoder_bit_exact(ctx):
@@ -92,28 +85,20 @@ def test_fp8_decode_every_code_through_the_kernel(ctx):
     assert f == -math.log(2.0)
 
 
-@pytest.mark.parametrize("K", [8, 16, 32, 64, 128, 256, 512, 1024, 2048])
-@pytest.mark.parametrize("N", [1, 65, 20_011])
+@pytest.mark.parametrize("K", sweeps.BF16_K)
+@pytest.mark.parametrize("N", sweeps.CODES_N)
 def test_bf16_kernel_against_oracle_on_codes(ctx, K, N):
-    X = _matrix(N, K, 10 + K)
-    g_ = np.random.default_rng(K + N)
-    beta = g_.standard_normal(K) / math.sqrt(K)
-    y = (g_.random(N) < 0.5).astype(np.uint8)
+    X, y, beta = sweeps.codes_case(N, K, "bf16")
     Qo = oracle.quantize_bf16(X)
-    f, g = eval_gpu(ctx, to_dev(Qo), to_dev(y), beta, 0.01, dtype=glm.GLM_BF16)
-    check_against_oracle(f, g, oracle.decode_bf16(Qo), y, beta, 0.01,
-                         X_for_oracle=Qo, oracle_kw={"dtype": "bf16"})
+    sweep_point(ctx, to_dev(Qo), to_dev(y), oracle.decode_bf16(Qo), y, beta, 0.01,
+                storage="bf16", dtype=glm.GLM_BF16, X_for_oracle=Qo, oracle_kw={"dtype": "bf16"})
 
 
-@pytest.mark.parametrize("K", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
-@pytest.mark.parametrize("N", [1, 65, 20_011])
+@pytest.mark.parametrize("K", sweeps.FP8_K)
+@pytest.mark.parametrize("N", sweeps.CODES_N)
 def test_fp8_kernel_against_oracle_on_codes(ctx, K, N):
-    X = _matrix(N, K, 20 + K)
-    g_ = np.random.default_rng(K * 3 + N)
-    beta = g_.standard_normal(K) / math.sqrt(K)
-    y = (g_.random(N) < 0.5).astype(np.uint8)
+    X, y, beta = sweeps.codes_case(N, K, "fp8")
     Qo, so = oracle.quantize_fp8(X)
-    f, g = eval_gpu(ctx, to_dev(Qo), to_dev(y), beta, 0.01, dtype=glm.GLM_FP8_E4M3,
-                    scale=to_dev(so))
-    check_against_oracle(f, g, oracle.decode_fp8(Qo, so), y, beta, 0.01,
-                         X_for_oracle=Qo, oracle_kw={"dtype": "fp8", "scale": so})
+    sweep_point(ctx, to_dev(Qo), to_dev(y), oracle.decode_fp8(Qo, so), y, beta, 0.01,
+                storage="fp8", dtype=glm.GLM_FP8_E4M3, scale=to_dev(so), X_for_oracle=Qo,
+                oracle_kw={"dtype": "fp8", "scale": so})

@@ -1,6 +1,5 @@
 """GPU tests of the several-beta pass (glm_logpost_grad_multi) and of the
 request server (continuous batching over resident data sets)."""
-import math
 import threading
 
 import numpy as np
@@ -11,9 +10,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
+import sweeps  # noqa: E402
 
 if torch.cuda.is_available():
-    from gpu_helpers import DEV, Ctx, bounds, to_dev  # noqa: E402
+    from gpu_helpers import DEV, Ctx, check_against_oracle, to_dev  # noqa: E402
     from paper_1310_1537_amd import glm  # noqa: E402
 
 
@@ -24,38 +24,37 @@ def ctx():
     c.close()
 
 
-def _data(N, K, seed, dtype=np.float32):
-    g = np.random.default_rng(seed)
-    X = g.standard_normal((N, K)).astype(dtype)
-    bt = g.standard_normal(K) / math.sqrt(K)
-    y = (g.random(N) < 1.0 / (1.0 + np.exp(-(X.astype(np.float64) @ bt)))).astype(np.uint8)
-    return X, y, bt
-
-
-def _betas(bt, n, seed):
-    return bt + 0.1 * np.random.default_rng(seed).standard_normal((n, len(bt)))
+_data = sweeps.serving_data
+_betas = sweeps.betas_near
 
 
 def _check(f, g, Xd, y, beta, prec, mean=None, storage="f32", Xo=None, okw=None):
-    fo, go = oracle.logpost_grad(Xd if Xo is None else Xo, y, beta, prec, mean, **(okw or {}))
-    bf, bg = bounds(Xd, y, beta, fo, go, storage)
-    assert abs(f - fo) <= bf, (f, fo, bf)
-    assert np.all(np.abs(g - go) <= bg)
+    check_against_oracle(f, g, Xd, y, beta, prec, mean, storage, X_for_oracle=Xo,
+                         oracle_kw=okw)
 
 
-@pytest.mark.parametrize("K", [8, 32, 128, 512])
-@pytest.mark.parametrize("nb", [1, 3, 8, 11])
+def _multi(ctx, ds, B, K, prec=0.01, M=None):
+    nb = len(B)
+    out = torch.full((nb, K + 1), float("nan"), dtype=torch.float64, device=DEV)
+    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), nb,
+                               glm.make_prior(prec, None if M is None else to_dev(M)), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("K", sweeps.MULTI_K)
+@pytest.mark.parametrize("nb", sweeps.MULTI_NB)
 def test_multi_against_oracle(ctx, K, nb):
+    """Every vector of the passes against the oracle, at its beta and (a
+    second call) at beta = 0 in every slot."""
     X, y, bt = _data(20_011, K, K + nb)
     B = _betas(bt, nb, 7)
     Xd, yd = to_dev(X), to_dev(y)
     ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
-    out = torch.full((nb, K + 1), float("nan"), dtype=torch.float64, device=DEV)
-    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), nb, glm.make_prior(0.01), out)
-    torch.cuda.synchronize()
-    o = out.cpu().numpy()
-    for b in range(nb):
-        _check(o[b, 0], o[b, 1:], X.astype(np.float64), y, B[b], 0.01)
+    for Bc in (B, np.zeros_like(B)):
+        o = _multi(ctx, ds, Bc, K)
+        for b in range(nb):
+            _check(o[b, 0], o[b, 1:], X.astype(np.float64), y, Bc[b], 0.01)
     glm.glm_dataset_unregister(ctx, ds)
 
 
@@ -71,7 +70,7 @@ def test_multi_per_vector_means_and_bf16(ctx):
     torch.cuda.synchronize()
     o = out.cpu().numpy()
     for b in range(5):
-        _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 2.0, M[b], Xo=Q,
+        _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 2.0, M[b], storage="bf16", Xo=Q,
                okw={"dtype": "bf16"})
     glm.glm_dataset_unregister(ctx, ds)
 
@@ -289,7 +288,7 @@ def test_server_fleet_launch_bitwise_and_oracle(ctx):
         if Q is None:
             _check(f, g, Xh, y, beta, 0.01)
         else:
-            _check(f, g, Xh, y, beta, 0.01, Xo=Q, okw={"dtype": "bf16"})
+            _check(f, g, Xh, y, beta, 0.01, storage="bf16", Xo=Q, okw={"dtype": "bf16"})
 
 
 @pytest.mark.parametrize("K", [128, 512])
@@ -317,7 +316,7 @@ def test_server_fleet_matrix_core_bitwise_and_oracle(ctx, K):
     for (i, beta), (f, g), (f1, g1) in zip(reqs, fleet, single):
         assert f == f1 and np.array_equal(g, g1), i
         Xh, y, _, Q = host[i]
-        _check(f, g, Xh, y, beta, 0.01, Xo=Q, okw={"dtype": "bf16"})
+        _check(f, g, Xh, y, beta, 0.01, storage="bf16", Xo=Q, okw={"dtype": "bf16"})
 
 
 def test_server_max_sets_argument(ctx):
@@ -363,13 +362,12 @@ def test_multi_bf16_matrix_core(ctx, K, nb):
     yd = to_dev(y)
     ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
     B = _betas(bt, nb, K + 3 * nb)
-    out = torch.full((nb, K + 1), float("nan"), dtype=torch.float64, device=DEV)
-    glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), nb, glm.make_prior(0.01), out)
-    torch.cuda.synchronize()
-    o = out.cpu().numpy()
     Xd = oracle.decode_bf16(Q)
-    for b in range(nb):
-        _check(o[b, 0], o[b, 1:], Xd, y, B[b], 0.01, Xo=Q, okw={"dtype": "bf16"})
+    for Bc in (np.zeros_like(B), B):
+        o = _multi(ctx, ds, Bc, K)
+        for b in range(nb):
+            _check(o[b, 0], o[b, 1:], Xd, y, Bc[b], 0.01, storage="bf16", Xo=Q,
+                   okw={"dtype": "bf16"})
     # slot 0 does not depend on what the other slots of its pass hold
     B2 = B.copy()
     B2[1:] = _betas(bt, nb - 1, K + 3 * nb + 1)
@@ -400,7 +398,7 @@ def test_multi_bf16_vector_alu_form(ctx, K, monkeypatch):
     glm.glm_dataset_unregister(ctx, ds)
     for env, o in res.items():
         for b in range(4):
-            _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 0.01, Xo=Q,
+            _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 0.01, storage="bf16", Xo=Q,
                    okw={"dtype": "bf16"})
     assert not np.array_equal(res["0"], res["1"])   # two different kernels ran
 
@@ -421,7 +419,7 @@ def test_multi_bf16_matrix_core_edges(ctx):
         o = out.cpu().numpy()
         for b in range(4):
             _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q[:n].reshape(n, K)), y[:n], B[b], 0.01,
-                   Xo=Q[:n].reshape(n, K), okw={"dtype": "bf16"})
+                   storage="bf16", Xo=Q[:n].reshape(n, K), okw={"dtype": "bf16"})
         glm.glm_dataset_unregister(ctx, ds)
     Qd, yd = to_dev(Q), to_dev(y)
     ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
@@ -433,7 +431,8 @@ def test_multi_bf16_matrix_core_edges(ctx):
     o = out.cpu().numpy()
     assert np.isnan(o[2, 0])
     for b in (0, 1, 3):
-        _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 0.01, Xo=Q, okw={"dtype": "bf16"})
+        _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 0.01, storage="bf16", Xo=Q,
+               okw={"dtype": "bf16"})
     glm.glm_dataset_unregister(ctx, ds)
 
 
@@ -465,7 +464,8 @@ def test_serving_workload_full_configuration(ctx):
         g = np.empty(len(beta))
         f = glm.glm_server_wait(srv, t, g)
         if dt == glm.GLM_BF16:
-            _check(f, g, oracle.decode_bf16(S), y, beta, 0.01, Xo=S, okw={"dtype": "bf16"})
+            _check(f, g, oracle.decode_bf16(S), y, beta, 0.01, storage="bf16", Xo=S,
+                   okw={"dtype": "bf16"})
         else:
             _check(f, g, S.astype(np.float64), y, beta, 0.01)
     st = glm.glm_server_stats(srv)

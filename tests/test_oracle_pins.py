@@ -350,6 +350,38 @@ def test_groups_and_multi_equal_plain_calls():
         assert outm[i, 0] == f and np.array_equal(outm[i, 1:], g)
 
 
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_groups_and_multi_on_codes_equal_plain_calls_on_decoded_slices(kind):
+    """The grouped and several-beta drivers on BF16 / FP8 codes (their own
+    byte strides and, for FP8, the column scales) give, bit for bit, the
+    plain function on the FP64-decoded rows of each group; the decoders are
+    pinned against torch's casts above.  Per-group prior means and the
+    Poisson family included."""
+    X32, y, _ = _data(1500, 24, 30, np.float32)
+    off = np.array([0, 1, 1, 300, 777, 1500])
+    G = len(off) - 1
+    rng = np.random.default_rng(31)
+    B = 0.2 * rng.standard_normal((G, 24))
+    M = rng.standard_normal((G, 24))
+    if kind == "bf16":
+        Q, s = oracle.quantize_bf16(X32), None
+        Xd = oracle.decode_bf16(Q)
+    else:
+        Q, s = oracle.quantize_fp8(X32)
+        Xd = oracle.decode_fp8(Q, s)
+    yp = np.minimum(rng.poisson(1.5, len(y)), 255).astype(np.uint8)
+    for yy, fam in ((y, "logistic"), (yp, "poisson")):
+        out = oracle.logpost_grad_groups(Q, yy, off, B, 2.0, M, dtype=kind, scale=s, family=fam)
+        for gi in range(G):
+            a, b = off[gi], off[gi + 1]
+            f, g = oracle.logpost_grad(Xd[a:b], yy[a:b], B[gi], 2.0, M[gi], family=fam)
+            assert out[gi, 0] == f and np.array_equal(out[gi, 1:], g), (kind, fam, gi)
+        outm = oracle.logpost_grad_multi(Q, yy, B, 0.5, M, dtype=kind, scale=s, family=fam)
+        for i in range(G):
+            f, g = oracle.logpost_grad(Xd, yy, B[i], 0.5, M[i], family=fam)
+            assert outm[i, 0] == f and np.array_equal(outm[i, 1:], g), (kind, fam, i)
+
+
 def test_rejects_invalid_arguments():
     X, y, beta = _data(10, 3, 20)
     with pytest.raises(ValueError):
