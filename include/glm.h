@@ -173,6 +173,25 @@ glm_status glm_dataset_unregister(glm_ctx* ctx, glm_dataset_id id);
 glm_status glm_logpost_grad(glm_ctx* ctx, glm_dataset_id id, const double* beta,
                             const glm_prior* prior, double* out, void* stream);
 
+/* The plain call for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc.  Same arguments, kernel, launch shape and result bits as
+ * glm_logpost_grad, but the block partials and tickets live in a static
+ * device array of 4 MiB per GPU (1,024 tickets; held until the process
+ * ends), set up once per device by glm_create, so this call allocates and
+ * frees nothing.  The array's tickets are zero between calls (each launch
+ * resets them); its partials keep the last call's values.
+ *   The launch needs 4 KiB + 8 (nblocks + ngroups)(1 + K) bytes, where
+ *   nblocks is at most one block per compute unit (256) and ngroups about
+ *   sqrt(nblocks): every K up to 1,900 fits at any N, wider rows only at
+ *   small N.  Larger needs return GLM_EINVAL (use glm_logpost_grad).
+ * Every such call on one GPU shares the one array: calls that may overlap
+ * on the device (different streams, or different contexts on the same GPU)
+ * race and give wrong results; serialise them on one stream.
+ * Errors: GLM_EINVAL, GLM_ENOTFOUND, GLM_EHIP. */
+glm_status glm_logpost_grad_noalloc(glm_ctx* ctx, glm_dataset_id id, const double* beta,
+                                    const glm_prior* prior, double* out, void* stream);
+
 /* Several coefficient vectors on one data set (e.g. many MCMC chains): f and
  * g for each of betas[0..nb-1], with X streamed once per pass of up to 8
  * vectors (the pass width is the largest of 8, 4, 2 that the instance's

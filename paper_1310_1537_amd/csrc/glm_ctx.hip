@@ -155,6 +155,8 @@ glm_status glm_create(int device, glm_ctx** out) {
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
+    glm_status st = static_scratch_setup(device);
+    if (st != GLM_OK) return st;
     GLM_HIP_CHECK(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
     *out = c.release();
     return GLM_OK;

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "fg_kernel.hpp"
 #include "runtime.hpp"
@@ -163,11 +164,86 @@ static glm_status launch_plain(glm_ctx* ctx, const Dataset& ds, const double* be
                         out, s, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------ static scratch
+//
+// The allocation-free plain call keeps its block partials, group partials and
+// tickets in this file-scope device array instead of the per-stream scratch.
+// Host code never passes the array's name to a kernel (on the host it is only
+// a stand-in for the symbol): its device address is looked up once per device
+// at context creation and kept in g_static_ptr.  Layout: kStaticTickets
+// tickets (zero between calls: cleared at set-up, reset by each launch's
+// merge), then the partials.
+constexpr size_t kStaticBytes = size_t(4) << 20;
+constexpr size_t kStaticTickets = 1024;
+static __device__ __align__(256) double scratch[kStaticBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+glm_status static_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices)
+        GLM_FAIL(GLM_EINVAL, "static scratch: device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_ptr[device]) return GLM_OK;
+    void* ptr = nullptr;
+    GLM_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) GLM_FAIL(GLM_EHIP, "static scratch: no device address for device %d", device);
+    GLM_HIP_CHECK(hipMemset(ptr, 0, kStaticTickets * sizeof(unsigned)));
+    GLM_HIP_CHECK(hipDeviceSynchronize());
+    g_static_ptr[device] = ptr;
+    return GLM_OK;
+}
+
+static glm_status launch_plain_static(glm_ctx* ctx, const Dataset& ds, const double* beta,
+                                      const glm_prior* prior, double* out, void* stream) {
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        base = g_static_ptr[ctx->device];
+    }
+    if (!base) GLM_FAIL(GLM_EHIP, "glm_logpost_grad_noalloc: static scratch not set up");
+    size_t np, ng, nc;
+    scratch_need(ds.plan, ds.d.K, 1, &np, &ng, &nc);
+    const size_t tick_bytes = kStaticTickets * sizeof(unsigned);
+    const size_t need = tick_bytes + (np + ng) * sizeof(double);
+    if (nc > kStaticTickets || need > kStaticBytes)
+        GLM_FAIL(GLM_EINVAL,
+                 "glm_logpost_grad_noalloc: this data set's launch needs %zu bytes of scratch "
+                 "(%zu tickets), the static scratch holds %zu bytes (%zu tickets); use "
+                 "glm_logpost_grad",
+                 need, nc, kStaticBytes, kStaticTickets);
+    Scratch s;
+    s.counters = static_cast<unsigned*>(base);
+    s.partials = reinterpret_cast<double*>(static_cast<char*>(base) + tick_bytes);
+    s.gpart = s.partials + np;
+    return launch_fused(ds.d, ds.plan, ds.plan.fn, 1, beta, prior->mean, nullptr, prior->prec, 1,
+                        out, &s, (hipStream_t)stream);
+}
+
 }  // namespace glmrt
 
 using namespace glmrt;
 
 extern "C" {
+
+glm_status glm_logpost_grad_noalloc(glm_ctx* ctx, glm_dataset_id id, const double* beta,
+                                    const glm_prior* prior, double* out, void* stream) {
+    clear_error();
+    if (!ctx || !beta || !prior || !out)
+        GLM_FAIL(GLM_EINVAL, "glm_logpost_grad_noalloc: NULL argument");
+    if (!(prior->prec >= 0.0))
+        GLM_FAIL(GLM_EINVAL, "glm_logpost_grad_noalloc: prior precision < 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->datasets.find(id);
+    if (it == ctx->datasets.end())
+        GLM_FAIL(GLM_ENOTFOUND, "glm_logpost_grad_noalloc: unknown data set %lld", (long long)id);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    return launch_plain_static(ctx, it->second, beta, prior, out, stream);
+}
 
 glm_status glm_logpost_grad(glm_ctx* ctx, glm_dataset_id id, const double* beta,
                             const glm_prior* prior, double* out, void* stream) {

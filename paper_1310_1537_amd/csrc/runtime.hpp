@@ -134,6 +134,10 @@ glm_status get_scratch(glm_ctx* ctx, void* stream, size_t n_partials, size_t n_g
 // Sets the device of ctx current on this thread.
 glm_status use_device(glm_ctx* ctx);
 
+// Looks up (once per device; the device must be current) the device address
+// of the allocation-free plain call's static scratch and clears its tickets.
+glm_status static_scratch_setup(int device);
+
 // Plan for a data set (defined with the kernel table).
 glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan);
 

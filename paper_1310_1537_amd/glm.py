@@ -92,6 +92,7 @@ _SIGS = {
     "glm_dataset_register": [_P, ctypes.POINTER(glm_dataset_desc), ctypes.POINTER(_I64)],
     "glm_dataset_unregister": [_P, _I64],
     "glm_logpost_grad": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P],
+    "glm_logpost_grad_noalloc": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P],
     "glm_logpost_grad_multi": [_P, _I64, _P, _I32, ctypes.POINTER(glm_prior), _P, _P],
     "glm_logpost_grad_host": [_P, _I64, _P, ctypes.POINTER(glm_prior), ctypes.POINTER(_D), _P],
     "glm_groupset_create": [_P, ctypes.POINTER(glm_dataset_desc), _P, _I32, _I32, _PP],
@@ -240,6 +241,11 @@ def make_prior(prec: float, mean=None, per_group: bool = False) -> glm_prior:
 def glm_logpost_grad(ctx: int, ds: int, beta, prior: glm_prior, out, stream=None) -> None:
     _check(_lib.glm_logpost_grad(ctx, ds, _ptr(beta), ctypes.byref(prior), _ptr(out),
                                  _stream(stream)))
+
+
+def glm_logpost_grad_noalloc(ctx: int, ds: int, beta, prior: glm_prior, out, stream=None) -> None:
+    _check(_lib.glm_logpost_grad_noalloc(ctx, ds, _ptr(beta), ctypes.byref(prior), _ptr(out),
+                                         _stream(stream)))
 
 
 def glm_logpost_grad_multi(ctx: int, ds: int, betas, nb: int, prior: glm_prior, out,
