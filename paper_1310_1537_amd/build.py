@@ -29,8 +29,16 @@ CFLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hdrs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    return max((os.path.getmtime(h) for h in hdrs), default=0.0)
+
+
+def _compile(src: str, incremental: bool = False, hdr_mtime: float = 0.0) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        if os.path.getmtime(obj) > max(os.path.getmtime(src), hdr_mtime):
+            return obj
     cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -38,11 +46,19 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every source (incremental=True: only those whose object is
+    older than the source or any header) and links the library."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    stale = glob.glob(os.path.join(OBJDIR, "*.o"))
+    keep = {os.path.join(OBJDIR, os.path.basename(s) + ".o") for s in srcs}
+    for o in stale:
+        if o not in keep:
+            os.remove(o)
+    hm = _headers_mtime()
     with ThreadPoolExecutor(min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, incremental, hm), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,5 +71,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -5,66 +5,11 @@
 #include <cstdlib>
 
 #include "fg_kernel.hpp"
+#include "multi_inst.hpp"
 #include "runtime.hpp"
 
 namespace glmrt {
 namespace {
-
-constexpr int WPB = 4;
-
-// R = 8 row slots per lane keeps the NB copies of beta and of the gradient
-// accumulators within the register file; instances with more than 32 values
-// of beta or gradient per lane (NB x columns per lane) are not built.  FP32
-// rows of 32 lanes with 8 vectors take 4 row slots instead, which fits two
-// waves per SIMD (255 registers) and runs 8 waves per block: 9-12 % faster
-// than 8 slots at one wave per SIMD.  (The other widths spill with 4 slots.)
-template <int DT, int LPR, int CPL, int NB>
-MultiInst minst() {
-    constexpr int VE = 16 / glmk::ElemSize<DT>::v;
-    if constexpr (NB * CPL * VE > 32) {
-        return MultiInst{};
-    } else if constexpr (DT == glmk::DT_F32 && LPR == 32 && CPL == 1 && NB == 8) {
-        MultiInst m;
-        m.fn = reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 4, 8, NB>);
-        m.R = 4;
-        m.NB = NB;
-        m.fleet = reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 4, 8, NB>);
-        m.wpb = 8;
-        return m;
-    } else {
-        return MultiInst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 8, WPB, NB>), 8, NB,
-                         reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 8, WPB, NB>)};
-    }
-}
-
-template <int DT, int NB>
-MultiInst mpick(int lpr, int cpl) {
-    if (cpl == 1) {
-        switch (lpr) {
-        case 1: return minst<DT, 1, 1, NB>();
-        case 2: return minst<DT, 2, 1, NB>();
-        case 4: return minst<DT, 4, 1, NB>();
-        case 8: return minst<DT, 8, 1, NB>();
-        case 16: return minst<DT, 16, 1, NB>();
-        case 32: return minst<DT, 32, 1, NB>();
-        case 64: return minst<DT, 64, 1, NB>();
-        }
-    } else if (lpr == 64) {
-        if (cpl == 2) return minst<DT, 64, 2, NB>();
-        if (cpl == 4) return minst<DT, 64, 4, NB>();
-    }
-    return MultiInst{};
-}
-
-template <int DT>
-MultiInst mpick_nb(int lpr, int cpl, int nb) {
-    switch (nb) {
-    case 8: return mpick<DT, 8>(lpr, cpl);
-    case 4: return mpick<DT, 4>(lpr, cpl);
-    case 2: return mpick<DT, 2>(lpr, cpl);
-    }
-    return MultiInst{};
-}
 
 // GLM_MFMA=0 keeps BF16 passes on the VALU kernels (for comparisons); read
 // at every choice of instance, so a process can time both forms.
@@ -84,10 +29,10 @@ MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max) {
         if (nb > nb_max) continue;
         MultiInst m;
         switch (dtype) {
-        case GLM_F64: m = mpick_nb<glmk::DT_F64>(lpr, cpl, nb); break;
-        case GLM_F32: m = mpick_nb<glmk::DT_F32>(lpr, cpl, nb); break;
-        case GLM_BF16: m = mpick_nb<glmk::DT_BF16>(lpr, cpl, nb); break;
-        case GLM_FP8_E4M3: m = mpick_nb<glmk::DT_FP8>(lpr, cpl, nb); break;
+        case GLM_F64: m = multi_pick_f64(lpr, cpl, nb); break;
+        case GLM_F32: m = multi_pick_f32(lpr, cpl, nb); break;
+        case GLM_BF16: m = multi_pick_bf16(lpr, cpl, nb); break;
+        case GLM_FP8_E4M3: m = multi_pick_fp8(lpr, cpl, nb); break;
         }
         if (m.fn) return m;
     }

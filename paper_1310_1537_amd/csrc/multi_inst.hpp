@@ -1,0 +1,77 @@
+// Kernel instances of the several-beta passes, by storage type.  Each
+// storage type's instances are compiled in a translation unit of their own
+// (glm_multi_<type>.hip), which keeps the build parallel.
+#pragma once
+
+#include "fg_kernel.hpp"
+#include "runtime.hpp"
+
+namespace glmrt {
+namespace multi_detail {
+
+constexpr int WPB = 4;
+
+// R = 8 row slots per lane keeps the NB copies of beta and of the gradient
+// accumulators within the register file; instances with more than 32 values
+// of beta or gradient per lane (NB x columns per lane) are not built.  FP32
+// rows of 32 lanes with 8 vectors take 4 row slots instead, which fits two
+// waves per SIMD (255 registers) and runs 8 waves per block: 9-12 % faster
+// than 8 slots at one wave per SIMD.  (The other widths spill with 4 slots.)
+template <int DT, int LPR, int CPL, int NB>
+MultiInst minst() {
+    constexpr int VE = 16 / glmk::ElemSize<DT>::v;
+    if constexpr (NB * CPL * VE > 32) {
+        return MultiInst{};
+    } else if constexpr (DT == glmk::DT_F32 && LPR == 32 && CPL == 1 && NB == 8) {
+        MultiInst m;
+        m.fn = reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 4, 8, NB>);
+        m.R = 4;
+        m.NB = NB;
+        m.fleet = reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 4, 8, NB>);
+        m.wpb = 8;
+        return m;
+    } else {
+        return MultiInst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 8, WPB, NB>), 8, NB,
+                         reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 8, WPB, NB>)};
+    }
+}
+
+template <int DT, int NB>
+MultiInst mpick(int lpr, int cpl) {
+    if (cpl == 1) {
+        switch (lpr) {
+        case 1: return minst<DT, 1, 1, NB>();
+        case 2: return minst<DT, 2, 1, NB>();
+        case 4: return minst<DT, 4, 1, NB>();
+        case 8: return minst<DT, 8, 1, NB>();
+        case 16: return minst<DT, 16, 1, NB>();
+        case 32: return minst<DT, 32, 1, NB>();
+        case 64: return minst<DT, 64, 1, NB>();
+        }
+    } else if (lpr == 64) {
+        if (cpl == 2) return minst<DT, 64, 2, NB>();
+        if (cpl == 4) return minst<DT, 64, 4, NB>();
+    }
+    return MultiInst{};
+}
+
+template <int DT>
+inline MultiInst mpick_nb(int lpr, int cpl, int nb) {
+    switch (nb) {
+    case 8: return mpick<DT, 8>(lpr, cpl);
+    case 4: return mpick<DT, 4>(lpr, cpl);
+    case 2: return mpick<DT, 2>(lpr, cpl);
+    }
+    return MultiInst{};
+}
+
+}  // namespace multi_detail
+
+// The instance of storage type dtype for rows of lpr lanes x cpl chunks with
+// nb vectors per pass (nb in {2, 4, 8}); fn == nullptr if none is built.
+MultiInst multi_pick_f64(int lpr, int cpl, int nb);
+MultiInst multi_pick_f32(int lpr, int cpl, int nb);
+MultiInst multi_pick_bf16(int lpr, int cpl, int nb);
+MultiInst multi_pick_fp8(int lpr, int cpl, int nb);
+
+}  // namespace glmrt
