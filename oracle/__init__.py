@@ -64,6 +64,12 @@ def lib():
         L.orc_bf16_to_double.restype = D
         L.orc_fp8_to_double.argtypes = [ctypes.c_uint8]
         L.orc_fp8_to_double.restype = D
+        U64p = ctypes.POINTER(ctypes.c_uint64)
+        L.orc_philox4x64_10.argtypes = [U64p, U64p, U64p]
+        L.orc_u01.argtypes = [ctypes.c_uint64]
+        L.orc_u01.restype = D
+        L.orc_polar_pair.argtypes = [ctypes.c_uint64] * 5 + [ctypes.POINTER(D)]
+        L.orc_polar_pair.restype = I
         L.orc_softplus.argtypes = [D]
         L.orc_softplus.restype = D
         L.orc_sigmoid.argtypes = [D]
@@ -260,3 +266,129 @@ def softplus(u: float) -> float:
 
 def sigmoid(u: float) -> float:
     return lib().orc_sigmoid(float(u))
+
+
+# ---------------------------------------------------------------- random numbers
+#
+# Counter-based Philox4x64-10 (Salmon et al., SC'11) and the streams the
+# library's on-device generator defines on it (purposes: 1 uniforms, 2
+# normals, 16 HMC momenta, 17 HMC accept uniforms; key = (seed, chain)).
+
+RNG_UNIFORM, RNG_NORMAL, RNG_HMC_MOMENTUM, RNG_HMC_ACCEPT = 1, 2, 16, 17
+
+
+def philox(ctr, key):
+    """The Philox4x64-10 block of a four-word counter under a two-word key."""
+    c = (ctypes.c_uint64 * 4)(*[int(v) & (2**64 - 1) for v in ctr])
+    k = (ctypes.c_uint64 * 2)(*[int(v) & (2**64 - 1) for v in key])
+    o = (ctypes.c_uint64 * 4)()
+    lib().orc_philox4x64_10(c, k, o)
+    return np.array(list(o), np.uint64)
+
+
+def u01(w) -> float:
+    """Uniform in (0, 1) from a 64-bit word (top 52 bits plus one half, times
+    2^-52)."""
+    return lib().orc_u01(int(w))
+
+
+def rng_uniforms(seed, chain, stream, offset, n, purpose=RNG_UNIFORM):
+    """Uniforms offset .. offset + n - 1 of a stream: value i is word i mod 4
+    of the block at counter (i / 4, 0, purpose, stream)."""
+    out = np.empty(n)
+    blk, cache = None, None
+    for j in range(n):
+        i = offset + j
+        if i // 4 != blk:
+            blk = i // 4
+            cache = philox((blk, 0, purpose, stream), (seed, chain))
+        out[j] = u01(cache[i % 4])
+    return out
+
+
+def polar_pair(seed, chain, purpose, stream, p):
+    """Normals 2p and 2p + 1 of a stream (Marsaglia's polar method) and the
+    attempts it took."""
+    z = (ctypes.c_double * 2)()
+    a = lib().orc_polar_pair(int(seed), int(chain), int(purpose), int(stream), int(p), z)
+    return z[0], z[1], a
+
+
+def rng_normals(seed, chain, stream, offset, n, purpose=RNG_NORMAL):
+    """Standard normals offset .. offset + n - 1 of a stream (value i is
+    component i mod 2 of pair i / 2)."""
+    out = np.empty(n)
+    for j in range(n):
+        i = offset + j
+        out[j] = polar_pair(seed, chain, purpose, stream, i // 2)[i % 2]
+    return out
+
+
+# ---------------------------------------------------------------- HMC
+#
+# Hamiltonian Monte Carlo, named in Sec. 4.2 among the samplers that use the
+# gradient.  The algorithm is the standard one (R. M. Neal, "MCMC using
+# Hamiltonian dynamics", Handbook of MCMC, 2011): momenta p ~ N(0, I), the
+# leapfrog integrator with step eps for n_leap steps on H = -f(beta) + p.p/2,
+# then a Metropolis correction accepting iff log U < H(start) - H(end).  The
+# random numbers come from the library's streams above: iteration t draws its
+# K momenta from purpose RNG_HMC_MOMENTUM, stream t (normal k of the
+# iteration), and its accept uniform as word 0 of the block at counter
+# (0, 0, RNG_HMC_ACCEPT, t).
+
+
+def hmc_momenta(seed, chain, t, K):
+    return rng_normals(seed, chain, t, 0, K, purpose=RNG_HMC_MOMENTUM)
+
+
+def hmc_log_u(seed, chain, t) -> float:
+    return math.log(u01(philox((0, 0, RNG_HMC_ACCEPT, t), (seed, chain))[0]))
+
+
+def leapfrog(grad_f, beta, g, p, eps, n_leap):
+    """n_leap leapfrog steps from (beta, p) with g = grad f(beta): half a
+    momentum step, then alternating full position and momentum steps, and a
+    closing half momentum step.  grad_f(b) returns (f, g).  Returns (beta, p,
+    f, g) at the end."""
+    p = p + 0.5 * eps * g
+    f = None
+    for l in range(n_leap):
+        beta = beta + eps * p
+        f, g = grad_f(beta)
+        if l < n_leap - 1:
+            p = p + eps * g
+    p = p + 0.5 * eps * g
+    return beta, p, f, g
+
+
+def hmc_chain(X, y, beta0, prec, n_iter, n_leap, eps, seed, chain, mean=None, follow=None,
+              iter0=0, **kw):
+    """n_iter HMC iterations (t = iter0 .. iter0 + n_iter - 1) from beta0 with
+    the oracle's f and g.  follow:
+    optional sequence of accept decisions to take instead of the oracle's own
+    (for replaying a chain whose decisions were taken elsewhere).  Returns a
+    dict with the final beta, f, g, the decisions, the oracle's log U and
+    H(start) - H(end) of every iteration and the f trace."""
+    def fg(b):
+        return logpost_grad(X, y, b, prec, mean, **kw)
+
+    beta = np.asarray(beta0, np.float64).copy()
+    f, g = fg(beta)
+    K = beta.size
+    acc = np.zeros(n_iter, np.uint8)
+    dH = np.zeros(n_iter)
+    logu = np.zeros(n_iter)
+    trace = np.zeros(n_iter)
+    for j in range(n_iter):
+        t = iter0 + j
+        p0 = hmc_momenta(seed, chain, t, K)
+        b1, p1, f1, g1 = leapfrog(fg, beta, g, p0, eps, n_leap)
+        dH[j] = (f1 - 0.5 * float(p1 @ p1)) - (f - 0.5 * float(p0 @ p0))
+        logu[j] = hmc_log_u(seed, chain, t)
+        a = logu[j] < dH[j] if follow is None else bool(follow[j])
+        acc[j] = a
+        if a:
+            beta, f, g = b1, f1, g1
+        trace[j] = f
+    return {"beta": beta, "f": f, "g": g, "accepted": acc, "dH": dH, "logu": logu,
+            "f_trace": trace}

@@ -313,3 +313,77 @@ int orc_quantize_fp8(const float* X, int64_t N, int K, int64_t ldx,
         }
     return 0;
 }
+
+/* ------------------------------------------------------------ random numbers
+ *
+ * Philox4x64-10, the counter-based generator of J. K. Salmon, M. A. Moraes,
+ * R. O. Dror and D. E. Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+ * (SC'11), written from its published definition: the output block is a keyed
+ * bijection of a four-word counter.  Each of the ten rounds forms the 128-bit
+ * products of counter words 0 and 2 with two fixed odd multipliers and
+ * recombines them as (hi(M1 x2) ^ x1 ^ k0, lo(M1 x2), hi(M0 x0) ^ x3 ^ k1,
+ * lo(M0 x0)); between rounds the two key words are advanced by Weyl constants
+ * (the golden ratio and sqrt(3) - 1 in 64-bit fixed point). */
+static const uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ULL, PHILOX_M1 = 0xCA5A826395121157ULL;
+static const uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ULL, PHILOX_W1 = 0xBB67AE8584CAA73BULL;
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        const unsigned __int128 p0 = (unsigned __int128)PHILOX_M0 * x0;
+        const unsigned __int128 p1 = (unsigned __int128)PHILOX_M1 * x2;
+        const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        const uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* Uniform in (0, 1) from a 64-bit word: its top 52 bits plus one half, times
+ * 2^-52; every step is exact in double, and the result lies in
+ * [2^-53, 1 - 2^-53]. */
+double orc_u01(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1.0p-52; }
+
+/* Standard normals by Marsaglia's polar method (G. Marsaglia and T. A. Bray,
+ * "A convenient method for generating normal variables", SIAM Review 6,
+ * 1964): a point (u, v) uniform in the square (-1, 1)^2 is accepted when
+ * 0 < s = u^2 + v^2 < 1, and then u c and v c with c = sqrt(-2 log(s) / s)
+ * are two independent standard normals.  Pair p of a stream takes its
+ * attempts a = 0, 1, ... from the blocks at counter (p, a / 2, purpose,
+ * stream), words 2 (a mod 2) and 2 (a mod 2) + 1; s is formed as
+ * fma(u, u, v v) so that the acceptance test is a fixed function of the
+ * bits.  Writes z[0..1]; returns the attempts used. */
+int orc_polar_pair(uint64_t seed, uint64_t chain, uint64_t purpose, uint64_t stream, uint64_t p,
+                   double z[2]) {
+    const uint64_t key[2] = {seed, chain};
+    z[0] = z[1] = 0.0;
+    /* at most 256 attempts: all miss the disc with probability below 10^-170,
+       and such a pair is (0, 0) */
+    for (int a = 0; a < 256; ++a) {
+        const uint64_t ctr[4] = {p, (uint64_t)(a >> 1), purpose, stream};
+        uint64_t w[4];
+        orc_philox4x64_10(ctr, key, w);
+        const double u = 2.0 * orc_u01(w[2 * (a & 1)]) - 1.0;
+        const double v = 2.0 * orc_u01(w[2 * (a & 1) + 1]) - 1.0;
+        const double s = fma(u, u, v * v);
+        if (s > 0.0 && s < 1.0) {
+            const double c = sqrt(-2.0 * log(s) / s);
+            z[0] = u * c;
+            z[1] = v * c;
+            return a + 1;
+        }
+    }
+    return 256;
+}
