@@ -58,12 +58,151 @@ def cpu_baseline(w, n_max: int, budget_s: float = 15.0, family: str = "logistic"
     return res, dt
 
 
+def host_info() -> dict:
+    """Host CPU as the CPU baselines see it: usable threads, logical CPUs and
+    the model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "model": model}
+
+
+def cpu_threads() -> int:
+    """Threads the all-threads CPU baselines use: the usable CPUs, at most 16
+    (the host share of one GPU)."""
+    return max(1, min(16, host_info()["nproc"]))
+
+
+def host_read_bandwidth(arr, threads: int, reps: int = 3) -> float:
+    """GB/s of a threaded integer sum over the bytes of a large host array
+    (each thread reduces its own slice; numpy releases the interpreter lock),
+    best of reps."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    flat = arr.reshape(-1).view(np.uint8)
+    n8 = flat.size // 8
+    v = flat[:n8 * 8].view(np.int64)
+    edges = np.linspace(0, v.size, threads + 1).astype(np.int64)
+    parts = [(int(a), int(b)) for a, b in zip(edges[:-1], edges[1:])]
+    best = 0.0
+    with ThreadPoolExecutor(threads) as ex:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            list(ex.map(lambda ab: int(np.add.reduce(v[ab[0]:ab[1]])), parts))
+            best = max(best, v.size * 8 / (time.perf_counter() - t0) / 1e9)
+    return best
+
+
+def numpy_som(X, y, beta, prec, family: str = "logistic", rows: int = 0, dtype=None, scale=None):
+    """The paper's naive sequence of maps in NumPy float64 with its threaded
+    BLAS: u = X beta, the per-row map, g = X^t r, over the first `rows` rows
+    (all if 0) of X upcast to float64 beforehand (the upcast is not timed).
+    Returns (seconds for the sample, sample rows)."""
+    import numpy as np
+
+    import oracle
+    n = X.shape[0] if rows <= 0 else min(rows, X.shape[0])
+    if dtype == "bf16":
+        Xd = oracle.decode_bf16(X[:n])
+    elif dtype == "fp8":
+        Xd = oracle.decode_fp8(X[:n], scale)
+    else:
+        Xd = np.asarray(X[:n], np.float64)
+    yd = np.asarray(y[:n], np.float64)
+    b = np.asarray(beta, np.float64)
+    t0 = time.perf_counter()
+    u = Xd @ b
+    if family == "poisson":
+        mu = np.exp(u)
+        f = float(np.sum(yd * u - mu))
+        r = yd - mu
+    else:
+        e = np.exp(-np.abs(u))
+        f = float(np.sum(yd * u - (np.maximum(u, 0.0) + np.log1p(e))))
+        r = yd - np.where(u >= 0.0, 1.0 / (1.0 + e), e / (1.0 + e))
+    g = Xd.T @ r
+    f -= 0.5 * prec * float(b @ b)
+    g -= prec * b
+    dt = time.perf_counter() - t0
+    return dt, n
+
+
+def cpu_baseline_report(n_units: float, unit: str, single, threaded, som, host: dict,
+                        sample: str, read_gbps: float | None) -> dict:
+    """The cpu_baseline record: value = the faster of the oracle on all host
+    threads (row blocks, fsum-combined) and single-threaded (cores: the
+    threads of that one), both given, with the NumPy float64 sequence of
+    maps beside them.  single / threaded: (seconds, units of work done[,
+    threads]) or None; som: (seconds, units) or None."""
+    rec = {"unit": unit, "kind": "oracle", "sample": sample, "host": dict(host)}
+    if read_gbps is not None:
+        rec["host"]["read_GBps"] = read_gbps
+    modes = []
+    if threaded:
+        rec["all_threads"] = {"value": threaded[1] / threaded[0] * n_units, "cores": threaded[2]}
+        modes.append(rec["all_threads"])
+    if single:
+        rec["single_thread"] = {"value": single[1] / single[0] * n_units, "cores": 1}
+        modes.append(rec["single_thread"])
+    if modes:
+        best = max(modes, key=lambda m: m["value"])
+        rec["value"], rec["cores"] = best["value"], best["cores"]
+    if som:
+        rec["numpy_som_f64"] = {"value": som[1] / som[0] * n_units,
+                                "note": "X @ beta, per-row map, X^t r in NumPy float64 with its "
+                                        "threaded BLAS (the paper's naive routine); X upcast "
+                                        "beforehand, untimed"}
+    return rec
+
+
 def _device_hold(torch, seconds: float) -> None:
     """Queues a spin of about `seconds` on the current stream (torch's
     cycle-count sleep kernel) when available."""
     sleep = getattr(torch.cuda, "_sleep", None)
     if sleep is not None:
         sleep(int(seconds * 2.4e9))
+
+
+MIN_WARM_S = 0.05
+
+
+def _warm(launch, warmup: int, min_s: float = MIN_WARM_S) -> int:
+    """At least `warmup` untimed launches, and more until about min_s of
+    device time has passed: the first ten or so back-to-back launches after
+    an idle spell run up to a third slower (clocks ramping; the kernel trace
+    of the 4M x 256 workload shows 650-790 us there against a steady 590-600
+    us), and a short timed run must not sit on that ramp.  Returns the
+    launches made."""
+    import torch
+    t0 = time.perf_counter()
+    n = 0
+    while n < warmup or time.perf_counter() - t0 < min_s:
+        launch(n)
+        n += 1
+        if n >= warmup and n % 4 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return n
 
 
 def _timed_evals(glm, lib, ctx, ds, prior, betas, outs, K, warmup, steps, stream):
@@ -82,19 +221,17 @@ def _timed_evals(glm, lib, ctx, ds, prior, betas, outs, K, warmup, steps, stream
         if st:
             raise glm.GlmError(st, glm.glm_last_error())
 
-    for i in range(warmup):
-        launch(i)
-    torch.cuda.synchronize()
+    nw = _warm(launch, warmup)
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
     for j in range(steps):
         ev0[j].record(stream)
-        launch(warmup + j)
+        launch(nw + j)
         ev1[j].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall, np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    return wall, np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)]), nw
 
 
 def bench_plain_big(args, poisson: bool = False):
@@ -121,8 +258,8 @@ def bench_plain_big(args, poisson: bool = False):
     ctx = glm.glm_create(0)
     ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y, family=family))
     prior = glm.make_prior(w.prec)
-    wall, kern_ms = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K, args.warmup,
-                                 args.steps, stream)
+    wall, kern_ms, n_warm = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K,
+                                         args.warmup, args.steps, stream)
     avg_ms = float(kern_ms.mean())
     print(f"[bench] {args.steps} evals in {wall:.3f} s; launch avg {avg_ms * 1e3:.1f} us",
           file=sys.stderr, flush=True)
@@ -150,7 +287,7 @@ def bench_plain_big(args, poisson: bool = False):
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": n_warm,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -176,16 +313,37 @@ def bench_plain_big(args, poisson: bool = False):
     }
 
     if not args.no_cpu_baseline:
-        res, dt = cpu_baseline(w, n_max=30, family="poisson" if poisson else "logistic")
+        fam = "poisson" if poisson else "logistic"
+        host = host_info()
+        thr = cpu_threads()
+        # the oracle on all host threads: every point the GPU evaluated among
+        # the first 11 (its error check), then more until about 10 s
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+        res = []
+        with ThreadPoolExecutor(thr) as pool:
+            t0 = time.perf_counter()
+            for i in range(min(total, n_traj)):
+                res.append(oracle.logpost_grad_blocks(w.X, w.y, w.betas[i], w.prec,
+                                                      threads=thr, family=fam, pool=pool))
+                if i >= 10 and time.perf_counter() - t0 > 10.0:
+                    break
+            dt_thr = time.perf_counter() - t0
         n = len(res)
         ef = max(abs(out_np[i][0] - res[i][0]) / abs(res[i][0]) for i in range(n))
         eg = max(np.linalg.norm(out_np[i][1:] - res[i][1]) / np.linalg.norm(res[i][1])
                  for i in range(n))
         result["err_vs_fp64"] = {"f_rel_max": ef, "g_rel_norm_max": eg, "points": n}
-        result["cpu_baseline"] = {"value": n / dt, "unit": "evals/s", "cores": 1,
-                                  "kind": "oracle",
-                                  "sample": f"first {n} trajectory points of the same "
-                                            f"N={N} K={K} workload, single-threaded FP64 C"}
+        single, dt1 = cpu_baseline(w, n_max=3, budget_s=5.0, family=fam)
+        som = numpy_som(w.X, w.y, w.betas[0], w.prec, fam, rows=N // 4)
+        result["cpu_baseline"] = cpu_baseline_report(
+            1.0, "evals/s", (dt1, len(single)), (dt_thr, n, thr),
+            (som[0], som[1] / N), host,
+            f"the first {n} trajectory points of the same N={N} K={K} workload on {thr} "
+            f"threads (row blocks, fsum-combined); {len(single)} single-threaded; the NumPy "
+            f"sequence of maps on the first {som[1]} rows, scaled to N",
+            host_read_bandwidth(w.X, thr))
     glm.glm_dataset_unregister(ctx, ds)
     glm.glm_destroy(ctx)
     return result
@@ -209,10 +367,15 @@ def _precision_cpu_leg(w, Xb_dev, Xq_dev, sc_dev):
 
     import oracle
     b0 = w.betas[0]
+    thr = cpu_threads()
     t0 = time.perf_counter()
-    refs = {"fp32": oracle.logpost_grad(w.X, w.y, b0, w.prec)}
-    seconds = time.perf_counter() - t0
+    refs = {"fp32": oracle.logpost_grad_blocks(w.X, w.y, b0, w.prec, threads=thr)}
+    seconds_thr = time.perf_counter() - t0
     N = w.X.shape[0]
+    n1 = N // 8   # single-threaded on an eighth of the rows, scaled
+    t0 = time.perf_counter()
+    oracle.logpost_grad(w.X[:n1], w.y[:n1], b0, w.prec)
+    seconds_1 = (time.perf_counter() - t0) * N / n1
     edges = np.linspace(0, N, 65).astype(np.int64)
     blocks = [(int(a), int(b)) for a, b in zip(edges[:-1], edges[1:]) if b > a]
     s8 = oracle.fp8_col_scales(w.X)
@@ -229,9 +392,18 @@ def _precision_cpu_leg(w, Xb_dev, Xq_dev, sc_dev):
     codes_equal = {"bf16": bool(np.array_equal(Xb_dev.cpu().numpy(), Qb)),
                    "fp8": bool(np.array_equal(Xq_dev.cpu().numpy(), Q8)
                                and np.array_equal(sc_dev.cpu().numpy(), s8))}
-    refs["bf16"] = oracle.logpost_grad(Qb, w.y, b0, w.prec, dtype="bf16")
-    refs["fp8"] = oracle.logpost_grad(Q8, w.y, b0, w.prec, dtype="fp8", scale=s8)
-    return {"seconds": seconds, "refs": refs, "codes_equal": codes_equal}
+    tf = {}
+    t0 = time.perf_counter()
+    refs["bf16"] = oracle.logpost_grad_blocks(Qb, w.y, b0, w.prec, threads=thr, dtype="bf16")
+    tf["bf16"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    refs["fp8"] = oracle.logpost_grad_blocks(Q8, w.y, b0, w.prec, threads=thr, dtype="fp8",
+                                             scale=s8)
+    tf["fp8"] = time.perf_counter() - t0
+    som = numpy_som(w.X, w.y, b0, w.prec, rows=N // 16)
+    return {"seconds_thr": seconds_thr, "seconds_1": seconds_1, "threads": thr,
+            "seconds_fmt": tf, "refs": refs, "codes_equal": codes_equal,
+            "som": (som[0], som[1] / N), "host": host_info()}
 
 
 def bench_precision(args):
@@ -269,8 +441,8 @@ def bench_precision(args):
                                     ("fp8", Xq, glm.GLM_FP8_E4M3, sc, 1)):
         ds = glm.glm_dataset_register(ctx, glm.make_desc(Xs, y, dtype=dt, col_scale=scale))
         outs = torch.empty((total, K + 1), dtype=torch.float64, device=dev)
-        wall, kern_ms = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K,
-                                     args.warmup, args.steps, stream)
+        wall, kern_ms, _ = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K,
+                                        args.warmup, args.steps, stream)
         bytes_alg = float(N) * K * es + N
         avg = float(kern_ms.mean())
         formats[name] = {"traffic": measured_traffic(f"fg_fused_precision_{name}"),
@@ -306,9 +478,19 @@ def bench_precision(args):
         "formats": formats,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = {"value": 1.0 / cpu["seconds"], "unit": "evals/s", "cores": 1,
-                                  "kind": "oracle", "sample": "one FP32 evaluation at the "
-                                  "first trajectory point, single-threaded FP64 C"}
+        result["err_vs_fp64"] = {
+            name: {"kernel": formats[name]["kernel_err"],
+                   "storage": formats[name].get("storage_err")} for name in formats}
+        result["cpu_baseline"] = cpu_baseline_report(
+            1.0, "evals/s (FP32 X)", (cpu["seconds_1"], 1), (cpu["seconds_thr"], 1,
+                                                              cpu["threads"]),
+            cpu["som"], cpu["host"],
+            f"one FP32 evaluation at the first trajectory point on {cpu['threads']} threads "
+            "(row blocks, fsum-combined); single-threaded on the first N/8 rows, scaled; the "
+            "NumPy sequence of maps on the first N/16 rows, scaled", None)
+        result["cpu_baseline"]["by_format_evals_per_s"] = {
+            "fp32": 1.0 / cpu["seconds_thr"],
+            **{k: 1.0 / v for k, v in cpu["seconds_fmt"].items()}}
     return result
 
 
@@ -356,15 +538,13 @@ def bench_batched(args):
         if st:
             raise glm.GlmError(st, glm.glm_last_error())
 
-    for i in range(args.warmup):
-        launch(i)
-    torch.cuda.synchronize()
+    n_warm = _warm(launch, args.warmup)
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
     for j in range(steps):
         ev0[j].record(stream)
-        launch(args.warmup + j)
+        launch(n_warm + j)
         ev1[j].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -391,11 +571,12 @@ def bench_batched(args):
     wall_plain = (time.perf_counter() - t0) / psteps
     for i in ids:
         glm.glm_dataset_unregister(ctx, i)
+    got0 = out[0].cpu().numpy()   # the launches with i % nt == 0 all evaluated B[0]
 
     result = {
         "metric": "logpost+grad evals/s (fused f+g, FP64 result) & HBM GB/s % peak",
         "value": steps / wall, "unit": "steps/s (all 2000 groups per step)", "n_gpus": 1,
-        "steps": steps, "warmup": args.warmup, "ms_per_step": wall / steps * 1e3,
+        "steps": steps, "warmup": n_warm, "ms_per_step": wall / steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"hierarchical: G={G} groups, N={N} rows, K={K}, FP32",
@@ -414,6 +595,39 @@ def bench_batched(args):
     }
     glm.glm_groupset_destroy(gs)
     glm.glm_destroy(ctx)
+    if not args.no_cpu_baseline:
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+        B0 = traj[0]
+        t0 = time.perf_counter()
+        ref = oracle.logpost_grad_groups(w.X, w.y, w.offsets, B0, w.prec, mean=w.mu)
+        dt1 = time.perf_counter() - t0
+        thr = cpu_threads()
+        # the groups split into thr ranges of about equal rows, one per thread
+        cuts = np.searchsorted(w.offsets, np.linspace(0, N, thr + 1)).clip(0, G)
+        cuts[0], cuts[-1] = 0, G
+        ranges = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+
+        def part(ab):
+            a, b = ab
+            o = w.offsets[a:b + 1]
+            return oracle.logpost_grad_groups(w.X[o[0]:o[-1]], w.y[o[0]:o[-1]], o - o[0],
+                                              B0[a:b], w.prec, mean=w.mu)
+
+        with ThreadPoolExecutor(thr) as pool:
+            t0 = time.perf_counter()
+            ref_t = np.concatenate(list(pool.map(part, ranges)))
+            dtt = time.perf_counter() - t0
+        assert np.array_equal(ref, ref_t)
+        fr = np.abs(got0[:, 0] - ref[:, 0]) / np.abs(ref[:, 0])
+        gr = np.linalg.norm(got0[:, 1:] - ref[:, 1:], axis=1) / np.linalg.norm(ref[:, 1:], axis=1)
+        result["err_vs_fp64"] = {"f_rel_max": float(fr.max()), "g_rel_norm_max": float(gr.max()),
+                                 "groups": G, "note": "every group at the first step's betas"}
+        result["cpu_baseline"] = cpu_baseline_report(
+            1.0, "steps/s (all 2000 groups per step)", (dt1, 1), (dtt, 1, len(ranges)), None,
+            host_info(), f"one full step (all {G} groups) single-threaded and split by groups "
+            f"over {len(ranges)} threads", None)
     return result
 
 
@@ -440,8 +654,8 @@ def bench_plain_small(args):
     ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
     prior = glm.make_prior(w.prec)
     stream = torch.cuda.current_stream()
-    wall, kern_ms = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K, args.warmup,
-                                 args.steps, stream)
+    wall, kern_ms, n_warm = _timed_evals(glm, glm.lib(), ctx, ds, prior, betas, outs, K,
+                                         args.warmup, args.steps, stream)
     # all points once more, in order, for the error check
     for i in range(nb):
         glm.glm_logpost_grad(ctx, ds, betas[i], prior, outs[i], stream)
@@ -459,6 +673,15 @@ def bench_plain_small(args):
     t0 = time.perf_counter()
     ref = [oracle.logpost_grad(w.X, w.y, b, w.prec) for b in w.betas]
     dt_cpu = time.perf_counter() - t0
+    host = host_info()
+    thr = cpu_threads()
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(thr) as pool:
+        t0 = time.perf_counter()
+        for b in w.betas:
+            oracle.logpost_grad_blocks(w.X, w.y, b, w.prec, threads=thr, pool=pool)
+        dt_thr = time.perf_counter() - t0
+    som_t = sum(numpy_som(w.X, w.y, b, w.prec)[0] for b in w.betas)
     ef = max(abs(got[i, 0] - ref[i][0]) / abs(ref[i][0]) for i in range(nb))
     eg = max(np.linalg.norm(got[i, 1:] - ref[i][1]) / max(np.linalg.norm(ref[i][1]), 1e-300)
              for i in range(nb))
@@ -483,8 +706,11 @@ def bench_plain_small(args):
                        "host_call_p99": float(np.percentile(lat_us, 99)),
                        "empty_kernel_roundtrip": probe_us},
         "err_vs_fp64": {"f_rel_max": ef, "g_rel_norm_max": eg, "points": nb},
-        "cpu_baseline": {"value": nb / dt_cpu, "unit": "evals/s", "cores": 1, "kind": "oracle",
-                         "sample": f"all {nb} points, single-threaded FP64 C"},
+        "cpu_baseline": cpu_baseline_report(
+            1.0, "evals/s", (dt_cpu, nb), (dt_thr, nb, thr), (som_t, nb), host,
+            f"all {nb} points: the oracle single-threaded and on {thr} threads (row blocks, "
+            "fsum-combined; at this size thread start-up dominates), and the NumPy sequence "
+            "of maps", None),
     }
 
 
@@ -507,9 +733,11 @@ def bench_serving(args):
     ctx = glm.glm_create(0)
     keep = []          # device tensors of the data sets
     datasets = []      # (K, beta_true, bytes)
+    host_sets = []     # (X float32, y) on the host, for the error check
     t0 = time.perf_counter()
     for i in range(nd):
         X32, y, bt = synth.serving_dataset(i, spec)
+        host_sets.append((X32, y))
         Xd = torch.from_numpy(X32).to(dev)
         yd = torch.from_numpy(y).to(dev)
         if spec.dtype[i] == "bf16":
@@ -566,6 +794,7 @@ def bench_serving(args):
         st = glm.glm_server_stats(srv)
         glm.glm_server_destroy(srv)
         return {"rate_offered": rate, "requests": n_req, "throughput": n_req / wall,
+                "GBps_streamed": st["bytes_streamed"] / wall / 1e9,
                 "latency_p50_us": st["latency_p50_us"], "latency_p99_us": st["latency_p99_us"],
                 "latency_mean_us": st["latency_mean_us"], "passes": st["passes"],
                 "mean_pass_width": st["betas_in_passes"] / max(1, st["passes"]),
@@ -588,9 +817,83 @@ def bench_serving(args):
         print(f"[bench] one/pass rate {r}: {res_1[-1]['throughput']:.0f} req/s "
               f"p50 {res_1[-1]['latency_p50_us']:.0f} us p99 {res_1[-1]['latency_p99_us']:.0f} us",
               file=sys.stderr, flush=True)
+    # binding budget: the same data sets given from pinned host memory to a
+    # server whose budget holds about a third of them, so that admissions and
+    # evictions churn under the open-loop load
+    budget_res = None
+    if args.serving_budget_gb >= 0:
+        pinned = []
+        for (Xk, yk, dt), (X32, y) in zip(keep, host_sets):
+            src = Xk.cpu() if dt == glm.GLM_BF16 else torch.from_numpy(X32)
+            pinned.append((src.pin_memory(), torch.from_numpy(y).pin_memory(), dt))
+        print("[bench] budget leg: host copies pinned", file=sys.stderr, flush=True)
+        largest = max(d[2] for d in datasets)
+        budget = int(args.serving_budget_gb * 1e9) if args.serving_budget_gb > 0 else \
+            int(max(1.25 * largest, 0.5 * total_bytes))
+        rate = args.serving_budget_rate
+        n_req = int(rate * args.serving_seconds)
+        srv = glm.glm_server_create(ctx, budget, 8, args.serving_streams, args.serving_slots,
+                                    1 << 22, args.serving_max_sets)
+        ids = [glm.glm_server_add_dataset(
+                   srv, glm.glm_dataset_desc(Xp.data_ptr(), Xp.shape[1], dt, None, yp.data_ptr(),
+                                             Xp.shape[0], Xp.shape[1], 0))
+               for Xp, yp, dt in pinned]
+        arr, chain = synth.poisson_arrivals(rate, n_req, n_chains, 20)
+        ds_of = np.array(ids, np.int64)[chain // 8]
+        ptrs = ptr_table[chain, np.arange(n_req) % pool]
+        precs = np.full(n_req, 0.01)
+        tickets = []
+        i = 0
+        t0 = time.perf_counter()
+        while i < n_req:
+            now = time.perf_counter() - t0
+            j = int(np.searchsorted(arr, now, side="right"))
+            if j > i:
+                tickets.append(glm.glm_server_submit_many(srv, ds_of[i:j], ptrs[i:j], precs[i:j]))
+                i = j
+        # past the deadline the server is shut down, which cancels what is
+        # still queued (the record then counts completed requests only)
+        import threading
+        timer = threading.Timer(max(0.0, args.serving_budget_deadline - (time.perf_counter() - t0)),
+                                glm.glm_server_shutdown, args=(srv,))
+        timer.start()
+        done = 0
+        for t in tickets:
+            glm.glm_server_wait_many(srv, t)
+            if (done + len(t)) // 2000 > done // 2000:
+                print(f"[bench] budget leg: {done + len(t)} of {n_req} requests done after "
+                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            done += len(t)
+        wall = time.perf_counter() - t0
+        timer.cancel()
+        timer.join()
+        st = glm.glm_server_stats(srv)
+        glm.glm_server_destroy(srv)
+        budget_res = {"hbm_budget_GB": budget / 1e9, "data_GB": total_bytes / 1e9,
+                      "rate_offered": rate, "requests": n_req, "completed": st["completed"],
+                      "cancelled_at_deadline": st["cancelled"],
+                      "throughput": st["completed"] / wall,
+                      "latency_p50_us": st["latency_p50_us"],
+                      "latency_p99_us": st["latency_p99_us"],
+                      "admissions": st["admissions"], "evictions": st["evictions"],
+                      "GB_admitted": st["bytes_admitted"] / 1e9,
+                      "GB_staged": st["bytes_staged"] / 1e9,
+                      "admit_GBps": st["bytes_admitted"] / max(st["admit_seconds"], 1e-9) / 1e9,
+                      "mean_pass_width": st["betas_in_passes"] / max(1, st["passes"]),
+                      "failed": st["failed"],
+                      "note": "host-sourced (pinned) data sets admitted on demand by the "
+                              "server's copy thread; evicted allocations reused"}
+        print(f"[bench] budget {budget / 1e9:.2f} GB rate {rate}: "
+              f"{budget_res['throughput']:.0f} req/s p50 {budget_res['latency_p50_us']:.0f} us "
+              f"p99 {budget_res['latency_p99_us']:.0f} us admissions {st['admissions']}",
+              file=sys.stderr, flush=True)
+        del pinned
+    check = None
+    if not args.no_cpu_baseline:
+        check = _serving_check(glm, ctx, keep, host_sets, ptr_table, args)
     glm.glm_destroy(ctx)
     top = res_b[-1]
-    return {
+    rec = {
         "metric": "logpost+grad requests/s served (fused f+g, FP64 result), p50/p99 latency",
         "value": top["throughput"], "unit": "requests/s", "n_gpus": 1,
         "steps": top["requests"], "warmup": nd, "ms_per_step": 1e3 / top["throughput"],
@@ -602,8 +905,73 @@ def bench_serving(args):
                    "hbm_budget_GB": 200, "max_beta_per_pass": 8, "slots": args.serving_slots,
                    "streams": args.serving_streams, "max_sets_per_launch": args.serving_max_sets or 32},
         "latency_us": {"p50": top["latency_p50_us"], "p99": top["latency_p99_us"]},
-        "by_rate": res_b, "one_request_per_pass": res_1,
+        "roofline": {"bound": "hbm", "achieved": top["GBps_streamed"], "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": top["GBps_streamed"] / PEAK_HBM_GBPS,
+                     "traffic": None,
+                     "note": "X and y bytes of every pass (one read per pass of up to 8 "
+                             "requests) over the wall time at the highest offered rate"},
+        "by_rate": res_b, "one_request_per_pass": res_1, "binding_budget": budget_res,
     }
+    if check is not None:
+        rec["err_vs_fp64"] = check["err"]
+        rec["cpu_baseline"] = check["cpu_baseline"]
+    return rec
+
+
+def _serving_check(glm, ctx, keep, host_sets, ptr_table, args):
+    """One server request per data set (chain 8i's first beta), f and g
+    checked against the oracle on the stored values (FP32 X, or the BF16
+    codes read back from the device); the oracle's time over the same 64
+    requests, single-threaded and on all host threads, gives the CPU
+    request rate (chains are uniform over data sets)."""
+    import ctypes
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    nd = len(keep)
+    srv = glm.glm_server_create(ctx, 200 * (1 << 30), 8, args.serving_streams,
+                                args.serving_slots, 1 << 16, args.serving_max_sets)
+    ids = [glm.glm_server_add_dataset(srv, glm.make_desc(X, y, dtype=dt), on_device=True)
+           for X, y, dt in keep]
+    got = []
+    for i in range(nd):
+        K = keep[i][0].shape[1]
+        beta = np.ctypeslib.as_array(ctypes.cast(int(ptr_table[8 * i, 0]),
+                                                 ctypes.POINTER(ctypes.c_double)), (K,)).copy()
+        t = glm.glm_server_submit(srv, ids[i], beta, 0.01)
+        g = np.empty(K)
+        f = glm.glm_server_wait(srv, t, g)
+        got.append((beta, f, g))
+    glm.glm_server_destroy(srv)
+    thr = cpu_threads()
+    worst_f = worst_g = 0.0
+    t_single = t_thr = 0.0
+    with ThreadPoolExecutor(thr) as pool:
+        for i in range(nd):
+            X32, y = host_sets[i]
+            dt = keep[i][2]
+            beta, f, g = got[i]
+            if dt == glm.GLM_BF16:
+                Xo, kw = keep[i][0].cpu().numpy(), {"dtype": "bf16"}
+            else:
+                Xo, kw = X32, {}
+            a = time.perf_counter()
+            rf, rg = oracle.logpost_grad_blocks(Xo, y, beta, 0.01, threads=thr, pool=pool, **kw)
+            t_thr += time.perf_counter() - a
+            a = time.perf_counter()
+            oracle.logpost_grad(Xo, y, beta, 0.01, **kw)
+            t_single += time.perf_counter() - a
+            worst_f = max(worst_f, abs(f - rf) / abs(rf))
+            worst_g = max(worst_g, float(np.linalg.norm(g - rg) / np.linalg.norm(rg)))
+    return {"err": {"f_rel_max": worst_f, "g_rel_norm_max": worst_g, "requests": nd,
+                    "note": "one request per data set through the server, against the oracle "
+                            "on the stored FP32 values or BF16 codes"},
+            "cpu_baseline": cpu_baseline_report(
+                1.0, "requests/s", (t_single, nd), (t_thr, nd, thr), None, host_info(),
+                f"the same {nd} requests (one per data set; chains are uniform over data "
+                f"sets), the oracle single-threaded and on {thr} threads", None)}
 
 
 def bench_copy(args):
@@ -792,9 +1160,41 @@ def bench_sampler(args):
                      "accept_rate": float(dev_acc.mean()),
                      "decisions_equal_host_driven": bool(np.array_equal(dev_acc[:n_host], host_acc)),
                      "steps_device": n_dev, "steps_host": n_host}
+        # HMC on the device (momenta and accept uniforms drawn there): step
+        # about half the posterior scale 1/sqrt(0.2 N), 5 leapfrog steps
+        n_it, L = (400, 5) if N < 100_000 else (20, 5)
+        eps = 0.5 / np.sqrt(0.2 * N)
+        acc_h = torch.empty(n_it, dtype=torch.uint8, device=dev)
+        b = torch.from_numpy(w.beta_true.copy()).to(dev)
+        glm.glm_hmc_run(ctx, ds, b, fg, 2, L, eps, 1, 1, prior, acc_h)
+        torch.cuda.synchronize()
+        b = torch.from_numpy(w.beta_true.copy()).to(dev)
+        t0 = time.perf_counter()
+        glm.glm_hmc_run(ctx, ds, b, fg, n_it, L, eps, 1, 1, prior, acc_h)
+        torch.cuda.synchronize()
+        hmc_s = time.perf_counter() - t0
+        out[name].update({"hmc_iterations_per_s": n_it / hmc_s,
+                          "hmc_us_per_leapfrog_step": hmc_s / (n_it * L) * 1e6,
+                          "hmc_leapfrog_steps": L, "hmc_eps": eps,
+                          "hmc_accept_rate": float(acc_h.cpu().numpy().mean())})
         print(f"[bench] sampler {name}: {out[name]}", file=sys.stderr, flush=True)
         glm.glm_dataset_unregister(ctx, ds)
         del X, y
+    # batch generation on the device: 2^26 values of each kind
+    n_rng = 1 << 26
+    buf = torch.empty(n_rng, dtype=torch.float64, device=dev)
+    rng = {}
+    for kname, kind in (("uniform", glm.GLM_RNG_UNIFORM), ("normal", glm.GLM_RNG_NORMAL),
+                        ("log_uniform", glm.GLM_RNG_LOG_UNIFORM)):
+        glm.glm_rng_fill(ctx, kind, 1, 2, 3, 0, n_rng, buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(5):
+            glm.glm_rng_fill(ctx, kind, 1, 2, 3, r * n_rng, n_rng, buf)
+        torch.cuda.synchronize()
+        rng[kname + "_per_s"] = 5 * n_rng / (time.perf_counter() - t0)
+    print(f"[bench] device generator: {rng}", file=sys.stderr, flush=True)
+    del buf
     glm.glm_destroy(ctx)
     sm = out["small_n10000_k20_f64"]
     return {
@@ -809,7 +1209,7 @@ def bench_sampler(args):
         "roofline": {"bound": "latency", "achieved": None, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": None, "traffic": None,
                      "note": "the small workload is bound by launch latency, not HBM"},
-        "workloads": out,
+        "workloads": out, "device_generator": rng,
     }
 
 
@@ -1000,7 +1400,111 @@ def bench_multi(args):
     return result
 
 
-WORKLOADS = {"copy": bench_copy, "plain_big": bench_plain_big, "precision": bench_precision,
+def bench_launch_fit(args):
+    """Per-launch time of the plain kernel against the bytes it streams:
+    N from 10,000 to 4,000,000 rows at K = 256 (FP32) and K = 32 (FP32), and
+    the 10,000 x 20 FP64 workload, each timed over back-to-back launches with
+    HIP events; a least-squares fit time = t0 + bytes / BW per K gives the
+    fixed cost t0 of a launch (ramp-up, tail and the cross-block merge)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1310_1537_amd import glm
+
+    dev = torch.device("cuda:0")
+    ctx = glm.glm_create(0)
+    stream = torch.cuda.current_stream()
+    reps = 200
+    rows = []
+
+    def time_ds(X, y, K, es, label):
+        ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y))
+        b = torch.zeros(K, dtype=torch.float64, device=dev)
+        b.normal_(0.0, 0.05)
+        out = torch.empty(K + 1, dtype=torch.float64, device=dev)
+        pr = glm.make_prior(0.01)
+        for _ in range(10):
+            glm.glm_logpost_grad(ctx, ds, b, pr, out, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            glm.glm_logpost_grad(ctx, ds, b, pr, out, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        N = X.shape[0]
+        rows.append({"case": label, "N": N, "K": K, "bytes": N * (K * es + 1), "us": us})
+        print(f"[bench] launch fit {label} N={N}: {us:.2f} us", file=sys.stderr, flush=True)
+        glm.glm_dataset_unregister(ctx, ds)
+
+    w = synth.plain_small(1)
+    time_ds(torch.from_numpy(w.X).to(dev), torch.from_numpy(w.y).to(dev), 20, 8, "f64_k20")
+    big = synth.plain_big(n_evals=1)
+    Xb = torch.from_numpy(big.X).to(dev)
+    yb = torch.from_numpy(big.y).to(dev)
+    for N in (10_000, 40_000, 160_000, 640_000, 1_000_000, 2_000_000, 4_000_000):
+        time_ds(Xb[:N], yb[:N], 256, 4, "f32_k256")
+    X32 = Xb[:, :32].contiguous()
+    for N in (10_000, 100_000, 500_000, 2_000_000, 4_000_000):
+        time_ds(X32[:N], yb[:N], 32, 4, "f32_k32")
+    fits = {}
+    for label in ("f32_k256", "f32_k32"):
+        r = [x for x in rows if x["case"] == label]
+        A = np.array([[1.0, x["bytes"]] for x in r])
+        t = np.array([x["us"] for x in r])
+        coef, *_ = np.linalg.lstsq(A, t, rcond=None)
+        fits[label] = {"t0_us": float(coef[0]), "GBps": float(1e-3 / coef[1]),
+                       "max_resid_us": float(np.max(np.abs(A @ coef - t)))}
+    glm.glm_destroy(ctx)
+    k = fits["f32_k256"]
+    return {"metric": "fixed per-launch cost of the fused kernel (fit of launch time to bytes)",
+            "value": k["t0_us"], "unit": "us", "higher_is_better": False, "n_gpus": 1,
+            "data": "synthetic", "config": {"workload": "plain kernel, N from 1e4 to 4e6"},
+            "fits": fits, "points": rows}
+
+
+def _sub_args(args, **kw):
+    """A copy of the command-line namespace with some fields replaced."""
+    d = dict(vars(args))
+    d.update(kw)
+    return argparse.Namespace(**d)
+
+
+# The other measured configurations in the default run: (name, function,
+# overrides).  Step counts are sized so that the whole default run stays
+# within a few minutes on one GPU.
+_SUB_CONFIGS = (
+    ("plain_small", lambda a: bench_plain_small(a), dict(steps=2000, warmup=50, latency_calls=400)),
+    ("precision", lambda a: bench_precision(a), dict(steps=20, warmup=5, n=0)),
+    ("batched", lambda a: bench_batched(a), dict(steps=200, warmup=10)),
+    ("serving", lambda a: bench_serving(a), dict(serving_seconds=1.0, serving_baseline=1)),
+)
+
+
+def bench_all(args):
+    """The headline 4M x 256 FP32 workload (the top-level record), then the
+    small, storage-precision, hierarchical and serving workloads, each as a
+    record under "configs" (an exception is recorded there, not raised)."""
+    result = bench_plain_big(args)
+    configs = {}
+    for name, fn, over in _SUB_CONFIGS:
+        t0 = time.perf_counter()
+        print(f"[bench] config {name}", file=sys.stderr, flush=True)
+        try:
+            rec = fn(_sub_args(args, **over))
+        except Exception as e:  # recorded, so that one failure does not hide the others
+            rec = {"error": f"{type(e).__name__}: {e}"}
+        rec["bench_wall_s"] = time.perf_counter() - t0
+        configs[name] = rec
+        print(f"[bench] config {name} done in {rec['bench_wall_s']:.1f} s", file=sys.stderr,
+              flush=True)
+    result["configs"] = configs
+    return result
+
+
+WORKLOADS = {"all": bench_all, "copy": bench_copy, "launch_fit": bench_launch_fit, "plain_big": bench_plain_big, "precision": bench_precision,
              "batched": bench_batched, "plain_small": bench_plain_small,
              "serving": bench_serving, "diff": bench_diff,
              "poisson": lambda a: bench_plain_big(a, poisson=True),
@@ -1012,7 +1516,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="plain_big", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="all", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=0, help="override N (precision workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-calls", type=int, default=200)
@@ -1022,6 +1526,12 @@ def main() -> int:
     ap.add_argument("--serving-streams", type=int, default=4)
     ap.add_argument("--serving-max-sets", type=int, default=0,
                     help="data sets per launch at most (0: the server default)")
+    ap.add_argument("--serving-budget-gb", type=float, default=0.0,
+                    help="HBM budget of the churn leg over host-sourced data sets (0: half "
+                         "the data, at least 1.25 times the largest set; negative: skip)")
+    ap.add_argument("--serving-budget-rate", type=int, default=20000)
+    ap.add_argument("--serving-budget-deadline", type=float, default=30.0,
+                    help="seconds after which the churn leg cancels what is still queued")
     ap.add_argument("--serving-baseline", type=int, default=1,
                     help="also run one request per pass at the first two rates")
     args = ap.parse_args()

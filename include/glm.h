@@ -287,8 +287,13 @@ glm_status glm_logpost_grad_batched(glm_ctx* ctx, glm_groupset* gs, const double
  * Data sets given with host pointers are copied to device memory on first
  * use (admission) if they fit hbm_budget_bytes together with the resident
  * ones; otherwise the least recently used data sets with no pass in flight
- * are evicted first, and if that is not enough the requests wait.  The
- * offload cost of one host round trip (Sec. 4.5) is paid per pass. */
+ * are evicted first, and if that is not enough the requests wait until
+ * passes finish.  Admission runs on a thread and a copy stream of its own
+ * (pageable sources through pinned staging buffers, pinned sources
+ * directly), so passes over resident data sets go on meanwhile; evicted
+ * allocations are kept for reuse within the budget instead of freed.  The
+ * latency quantiles come from a fixed histogram of 2 % buckets.  The offload
+ * cost of one host round trip (Sec. 4.5) is paid per pass. */
 typedef struct glm_server glm_server;
 
 typedef struct {
@@ -314,6 +319,13 @@ typedef struct {
     double latency_p99_us;
     double latency_mean_us;
     uint64_t launches;           /* kernel launches that carried the passes         */
+    uint64_t bytes_streamed;     /* sum over passes of N (K size + 1): X and y read */
+    uint64_t bytes_admitted;     /* data-set bytes copied to HBM by admissions      */
+    double admit_seconds;        /* time the admission thread spent on them         */
+    uint64_t cached_bytes;       /* evicted allocations kept for reuse (they count
+                                    against the budget and are released as needed) */
+    uint64_t bytes_staged;       /* of bytes_admitted, copied through the pinned
+                                    staging buffers (pageable sources)              */
 } glm_server_metrics;
 
 /* Starts the scheduler thread.  Errors: GLM_EINVAL, GLM_EHIP. */
@@ -323,8 +335,9 @@ glm_status glm_server_create(glm_ctx* ctx, const glm_server_config* cfg, glm_ser
  * pointers (X, y, col_scale) that the caller keeps valid until the server is
  * destroyed; the server copies them to HBM when needed.  on_device != 0:
  * device pointers, always resident (counted in the budget, never evicted).
- * Errors: as glm_dataset_register; GLM_EBUDGET if the data set alone (or, on
- * device, with the resident ones) exceeds the budget. */
+ * Errors: as glm_dataset_register; GLM_EBUDGET if the data set does not fit
+ * the budget beside the device-resident data sets already added (then a
+ * host-sourced one could never be admitted). */
 glm_status glm_server_add_dataset(glm_server* srv, const glm_dataset_desc* desc, int32_t on_device,
                                   glm_dataset_id* out);
 
@@ -467,6 +480,57 @@ glm_status glm_diff_commit(glm_ctx* ctx, glm_dataset_id colset, double* u, doubl
 glm_status glm_mh_run(glm_ctx* ctx, glm_dataset_id id, double* beta, double* fg,
                       const double* incs, const double* logu, int32_t n_steps,
                       const glm_prior* prior, uint8_t* accepted, double* f_trace, void* stream);
+
+/* Runs n_iter iterations of Hamiltonian Monte Carlo on the device (Sec. 4.2
+ * names HMC among the samplers that consume the gradient; the leapfrog
+ * integrator and the Metropolis correction are the standard ones, R. M. Neal,
+ * "MCMC using Hamiltonian dynamics", 2011).  Each iteration draws momenta
+ * p ~ N(0, I), takes n_leap leapfrog steps of size eps on
+ * H = -f(beta) + |p|^2 / 2 (one fused f + g evaluation per step, whose last
+ * block moves momenta and position) and accepts iff
+ * log U < H(start) - H(end).  Momenta and U come from the counter-based
+ * streams of glm_rng_fill with key (seed, chain): iteration t's momenta are
+ * the normals of purpose 16, stream t; its U is word 0 of the block at
+ * counter (0, 0, 17, t); so the chain is reproducible off the device.  The
+ * iterations are t = iter0 .. iter0 + n_iter - 1: a chain run in pieces
+ * (iter0 = the iterations already run, beta = its state) is the same chain.
+ *   beta   device, K doubles: the start on entry, the last state on return
+ *   fg     device, 1 + K doubles: f and g at the last state
+ *   accepted (n_iter bytes) and f_trace (n_iter doubles: f of the state
+ *   after iteration t): device, may be NULL
+ * Async on `stream`, n_iter * n_leap + 1 fused launches and no host round
+ * trip.  Errors: GLM_EINVAL (n_leap < 1, eps not > 0, iter0 + n_iter >= 2^32,
+ * ...), GLM_ENOTFOUND,
+ * GLM_ENOMEM, GLM_EHIP. */
+glm_status glm_hmc_run(glm_ctx* ctx, glm_dataset_id id, double* beta, double* fg, int32_t n_iter,
+                       int32_t n_leap, double eps, uint64_t seed, uint64_t chain, uint32_t iter0,
+                       const glm_prior* prior, uint8_t* accepted, double* f_trace, void* stream);
+
+/* ------------------------------------------------------- random numbers */
+
+/* Batch generation of random deviates on the device (the paper's batch RNG,
+ * Sec. 4.4 and Sec. 5.2, with the buffers filled by the GPU): values
+ * offset .. offset + n - 1 of one stream of the counter-based generator
+ * Philox4x64-10 (Salmon et al., SC'11) under key (seed, chain):
+ *   GLM_RNG_UNIFORM      U_i = ((w >> 12) + 1/2) 2^-52 in (0, 1), w = word
+ *                        i mod 4 of the block at counter (i / 4, 0, 1, stream_id)
+ *   GLM_RNG_LOG_UNIFORM  log U_i of the same U_i (e.g. Metropolis accept tests)
+ *   GLM_RNG_NORMAL       scale * z_i, standard normals by Marsaglia's polar
+ *                        method: pair p tries blocks at counter
+ *                        (p, a / 2, 2, stream_id), words 2 (a mod 2) and
+ *                        2 (a mod 2) + 1, as u, v = 2 U - 1, until
+ *                        0 < s = fma(u, u, v v) < 1; then z = (u, v) c with
+ *                        c = sqrt(-2 log(s) / s)
+ * (UNIFORM and LOG_UNIFORM values are scaled by 1, not by scale.)  Any value
+ * depends only on its index, so fills of adjacent ranges join seamlessly.
+ *   out  device, n doubles.  Async on `stream`.
+ * Errors: GLM_EINVAL (unknown kind, n < 0, offset + n >= 2^63), GLM_EHIP. */
+#define GLM_RNG_UNIFORM      1
+#define GLM_RNG_NORMAL       2
+#define GLM_RNG_LOG_UNIFORM  3
+glm_status glm_rng_fill(glm_ctx* ctx, int32_t kind, uint64_t seed, uint64_t chain,
+                        uint64_t stream_id, uint64_t offset, int64_t n, double scale, double* out,
+                        void* stream);
 
 /* -------------------------------------------------------- boundary probe */
 

@@ -165,7 +165,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
     // The barrier orders every wave's partial stores before wave 0's
     // agent-scope release fence; the tickets themselves can then be relaxed.
     __syncthreads();
-    if (wave == 0) __threadfence();
+    if (wave == 0) release_agent();
     __shared__ unsigned s_win[NT];
     for (int qb = q0; qb < q1; qb += NT) {
         if (wave == 0) {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
                                                              __HIP_MEMORY_SCOPE_AGENT);
                 s_win[qq - qb] = prev == (unsigned)(p.group_blocks[g] - 1) ? 1u : 0u;
             }
-            __threadfence();   // acquire side: tiles published by other blocks
+            acquire_agent();   // tiles published by other blocks
         }
         __syncthreads();
         // The won groups are spread over the waves (entry j to wave

@@ -16,8 +16,12 @@
 //
 // Per batch:
 //   1. issue all R*CPL 16-byte loads (plus the y bytes of owned rows);
-//   2. per-lane partial dot products with beta split as beta_hi + beta_lo
-//      (two FP32 numbers) so that no rounding of the FP64 beta leaks into u;
+//   2. per-lane partial dot products in FP64: every stored value is exact in
+//      FP64 (FP32, BF16 and FP8 codes alike) and is multiplied by the FP64
+//      beta with FP64 FMAs, so u carries FP64 rounding only.  Without packed
+//      FP32 math an FP64 FMA issues at the rate of an FP32 FMA, so the
+//      conversion plus one FP64 FMA per value costs what two FP32 FMAs on a
+//      hi + lo split of beta cost, at 2^-53 instead of 2^-24 per rounding;
 //   3. a transposed butterfly reduction across the LPR lanes of a segment
 //      leaves each lane with complete u values of R/LPR rows (or one row
 //      shared by LPR/R lanes), so the TR map runs one row per lane, in FP64;
@@ -41,6 +45,7 @@
 
 #include <type_traits>
 
+#include "rng.hpp"
 #include "tr_math.hpp"
 
 namespace glmk {
@@ -57,20 +62,32 @@ template <> struct ElemSize<DT_F32> { static constexpr int v = 4; };
 template <> struct ElemSize<DT_BF16> { static constexpr int v = 2; };
 template <> struct ElemSize<DT_FP8> { static constexpr int v = 1; };
 
-// A random-walk Metropolis chain advanced by the evaluation kernel itself:
-// the launch evaluates f and g at the proposal beta_prop (its beta), and the
-// last block then takes the accept step and writes the next proposal, so a
-// chain costs one launch per step.
+// A chain advanced by the evaluation kernel itself: the launch evaluates f
+// and g at the point beta_prop (its beta), and the last block then takes the
+// sampler's step and writes the next point to evaluate, so a chain costs one
+// launch per evaluation.
+//   kind 0, random-walk Metropolis: one evaluation per step; increments and
+//     log-uniforms are inputs.
+//   kind 1, Hamiltonian Monte Carlo: n_leap evaluations per iteration
+//     (leapfrog positions); momenta and the accept uniform are drawn on the
+//     device from the counter-based streams of rng.hpp.
 struct ChainParams {
     double* beta;             // K, the chain state
     double* fg;               // 1 + K, f and g at the state
-    double* beta_prop;        // K, the proposal being evaluated (this launch's beta)
-    const double* incs;       // n_steps x K proposal increments
-    const double* logu;       // n_steps log-uniforms
-    unsigned* step;           // step counter t
-    int n_steps;
+    double* beta_prop;        // K, the point being evaluated (this launch's beta)
+    const double* incs;       // MH: n_steps x K proposal increments
+    const double* logu;       // MH: n_steps log-uniforms
+    unsigned* step;           // MH: step t; HMC: iteration t, then leapfrog position l
+    int n_steps;              // MH steps or HMC iterations
     uint8_t* accepted;        // n_steps or nullptr
     double* f_trace;          // n_steps or nullptr
+    int kind = 0;             // 0 MH, 1 HMC
+    int n_leap = 0;           // HMC: leapfrog steps per iteration
+    double eps = 0.0;         // HMC: leapfrog step
+    double* mom = nullptr;    // HMC: K momenta
+    double* h0 = nullptr;     // HMC: f - |p|^2 / 2 at the start of the iteration
+    uint64_t seed = 0, chain_id = 0;   // HMC: generator key
+    unsigned iter0 = 0;       // HMC: index of the first iteration (its random streams)
 };
 
 // Kernel parameters (passed by value).  nb coefficient vectors are
@@ -202,15 +219,6 @@ __device__ __forceinline__ double xstep(double a, double b, bool up) {
     return k + g;
 }
 
-struct HiLo {
-    float h, l;
-};
-
-template <int D>
-__device__ __forceinline__ HiLo xstep(HiLo a, HiLo b, bool up) {
-    return HiLo{xstep<D>(a.h, b.h, up), xstep<D>(a.l, b.l, up)};
-}
-
 // Transposed reduction over the LPR lanes of a segment (LPR a power of two,
 // segments aligned).  On entry v[j] is this lane's partial of row slot j
 // (j < R).  Afterwards, if R >= LPR, v[i] (i < R/LPR) holds the complete sum
@@ -333,11 +341,115 @@ __device__ __forceinline__ void ordered_sums(const double* a, int n, int64_t str
     }
 }
 
+// Sum of one value per thread over a block of NT threads, returned to every
+// thread: wave butterflies, then the wave totals in wave order.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double s_w[NT / 64];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += s_w[w];
+    return t;
+}
+
+// Starts HMC iteration t from the chain state (beta, fg): momenta p ~ N(0, I)
+// from the stream of iteration t, h0 = f - |p|^2 / 2, the first half
+// momentum step and the first position step into beta_prop, leapfrog
+// position 1.  Run by all NT threads of one block.
+template <int NT>
+__device__ __forceinline__ void hmc_begin(const ChainParams& c, unsigned t, int K) {
+    double kin = 0.0;
+    const double he = 0.5 * c.eps;
+    for (int q = threadIdx.x; 2 * q < K; q += NT) {
+        double z[2];
+        polar_pair(c.seed, c.chain_id, RNG_HMC_MOMENTUM, t, (uint64_t)q, z[0], z[1]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 2 * q + h;
+            if (k < K) {
+                kin = fma(z[h], z[h], kin);
+                const double m = z[h] + he * c.fg[1 + k];
+                c.mom[k] = m;
+                c.beta_prop[k] = c.beta[k] + c.eps * m;
+            }
+        }
+    }
+    kin = block_sum<NT>(kin);
+    if (threadIdx.x == 0) {
+        c.h0[0] = c.fg[0] - 0.5 * kin;
+        c.step[0] = t;
+        c.step[1] = 1;
+    }
+}
+
+// One HMC evaluation's step, after f and g at beta_prop (fg_prop) are
+// written: inside the trajectory a full momentum step and the next position;
+// at its end the closing half momentum step, the accept test
+// log U_t < (f' - |p'|^2 / 2) - h0, the state update and the start of the next
+// iteration.  Run by all threads of the last block.
+template <int NT>
+__device__ __forceinline__ void hmc_step(const ChainParams& c, const double* fg_prop, int K) {
+    __shared__ unsigned s_tl[2];
+    __shared__ int s_acc;
+    if (threadIdx.x == 0) {
+        s_tl[0] = c.step[0];
+        s_tl[1] = c.step[1];
+    }
+    __syncthreads();
+    const unsigned t = s_tl[0], l = s_tl[1];
+    if ((int)l < c.n_leap) {
+        for (int k = threadIdx.x; k < K; k += NT) {
+            const double m = c.mom[k] + c.eps * fg_prop[1 + k];
+            c.mom[k] = m;
+            c.beta_prop[k] = c.beta_prop[k] + c.eps * m;
+        }
+        if (threadIdx.x == 0) c.step[1] = l + 1;
+        return;
+    }
+    double kin = 0.0;
+    const double he = 0.5 * c.eps;
+    for (int k = threadIdx.x; k < K; k += NT) {
+        const double m = c.mom[k] + he * fg_prop[1 + k];
+        kin = fma(m, m, kin);
+    }
+    kin = block_sum<NT>(kin);
+    if (threadIdx.x == 0) {
+        const double dH = (fg_prop[0] - 0.5 * kin) - c.h0[0];
+        const Block4 b = philox4x64_10(0, 0, RNG_HMC_ACCEPT, t, c.seed, c.chain_id);
+        s_acc = log_f64(u01(b.w[0])) < dH ? 1 : 0;
+    }
+    __syncthreads();
+    const int acc = s_acc;
+    if (acc) {
+        for (int k = threadIdx.x; k <= K; k += NT) c.fg[k] = fg_prop[k];
+        for (int k = threadIdx.x; k < K; k += NT) c.beta[k] = c.beta_prop[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (c.accepted) c.accepted[t - c.iter0] = (uint8_t)acc;
+        if (c.f_trace) c.f_trace[t - c.iter0] = c.fg[0];
+    }
+    if (t + 1 - c.iter0 < (unsigned)c.n_steps) {
+        hmc_begin<NT>(c, t + 1, K);
+    } else if (threadIdx.x == 0) {
+        c.step[0] = t + 1;
+    }
+}
+
 // Accept iff log U_t < f(beta_prop) - f(beta); on acceptance the state takes
 // the proposal's beta, f and g; then beta_prop = beta + incs[t + 1] and t + 1.
 // Run by all threads of the last block after fg_prop (1 + K) is written.
 template <int NT>
 __device__ __forceinline__ void chain_step(const ChainParams& c, const double* fg_prop, int K) {
+    if (c.kind == 1) {
+        hmc_step<NT>(c, fg_prop, K);
+        return;
+    }
     __shared__ int s_acc;
     __shared__ unsigned s_t;
     if (threadIdx.x == 0) {
@@ -364,6 +476,14 @@ __device__ __forceinline__ void chain_step(const ChainParams& c, const double* f
     }
 }
 
+// Agent-scope release and acquire fences.  Across the blocks of a launch the
+// merge publishes partials with a release before a relaxed ticket increment,
+// and only the block that completes a count acquires before reading the
+// others' partials (a full fence on both sides would also invalidate the L2
+// of every finishing block and write it back twice).
+__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Called by every thread of every block after the block has written its
 // partial (NB x (1 + K) doubles at partials + blk * NB * (1 + K), blk being
 // the block's index among the p.nblocks blocks of this evaluation).  NT is
@@ -382,11 +502,11 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     // release fence; the ticket itself can then be a relaxed atomic.
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        release_agent();
         const unsigned prev = __hip_atomic_fetch_add(&p.counters[grp], 1u, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == (unsigned)(b1 - b0 - 1)) ? 1u : 0u;
-        if (s_last) __threadfence();   // acquire side
+        if (s_last) acquire_agent();
     }
     __syncthreads();
     if (!s_last) return;
@@ -411,11 +531,11 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     if (ngroups > 1) {
         // second level: the last group to finish adds the group sums
         if (threadIdx.x == 0) {
-            __threadfence();
+            release_agent();
             const unsigned prev = __hip_atomic_fetch_add(&p.counters[ngroups], 1u, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
             s_last = (prev == (unsigned)(ngroups - 1)) ? 1u : 0u;
-            if (s_last) __threadfence();
+            if (s_last) acquire_agent();
         }
         __syncthreads();
         if (!s_last) return;
@@ -514,7 +634,13 @@ struct WaveTile {
     // all of them; NTR is the number of maps a lane then evaluates.
     static constexpr bool SPLIT_TR = REP > 1 && NB > 1;
     static constexpr int NTR = SPLIT_TR ? (NB + REP - 1) / REP : 1;
-    using rtype = typename std::conditional<F64, double, float>::type;
+    // The gradient products r_n x_nk in FP64 (r kept in FP64): FP64 storage,
+    // and FP32 storage with one coefficient vector (the plain and hierarchical
+    // kernels), where the vector ALU has room for the conversion.  Otherwise
+    // (BF16, FP8, several vectors) r is rounded to FP32 and the products are
+    // summed in FP32 over the R rows of a batch, then added in FP64.
+    static constexpr bool G64 = F64 || (DT == DT_F32 && NB == 1);
+    using rtype = typename std::conditional<G64, double, float>::type;
 
     struct Tile {
         u32x4 x[R][CPL];
@@ -530,8 +656,7 @@ struct WaveTile {
     uint32_t loff[CPL];      // byte offset of this lane's chunk i in row slot 0
     uint32_t yoff[OWN];      // row slot (within a batch) of each owned row
     bool unique;             // this lane accounts its owned rows in f
-    float bh[NB][CPL][VE], bl[NB][CPL][VE];   // beta = bh + bl (FP32 storage kinds)
-    double bd[NB][CPL][VE];                   // beta (FP64 storage)
+    double bd[NB][CPL][VE];                   // beta (FP8: times the column scale)
     double g64[NB][CPL][VE];                  // this lane's gradient columns
     double facc[NB];
     double fk[NTR];                           // f of slot cl % REP + k * REP (SPLIT_TR)
@@ -583,12 +708,7 @@ struct WaveTile {
                     v = beta[col(i, e)];
                     if constexpr (DT == DT_FP8) v *= (double)scale[col(i, e)];
                 }
-                if constexpr (F64) {
-                    bd[b][i][e] = v;
-                } else {
-                    bh[b][i][e] = (float)v;
-                    bl[b][i][e] = (float)(v - (double)bh[b][i][e]);
-                }
+                bd[b][i][e] = v;
             }
         }
     }
@@ -671,27 +791,27 @@ struct WaveTile {
 #pragma unroll
                 for (int o = 0; o < OWN; ++o) uo[o] = v[o];
             } else {
-                HiLo v[R];
+                double v[R];
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    float sh = 0.0f, sl = 0.0f;
+                    double sacc = 0.0;
 #pragma unroll
                     for (int i = 0; i < CPL; ++i) {
                         u32x4 raw = t.x[j][i];
-                        if constexpr (VE > 4 && NB > 1) asm volatile("" : "+v"(raw));
+                        // with several vectors, convert again per vector rather
+                        // than keep the converted tile alive (2 registers per
+                        // value): the empty asm hides that raw is unchanged
+                        if constexpr (NB > 1) asm volatile("" : "+v"(raw));
                         float xv[VE];
                         decode_chunk<DT>(raw, xv);
 #pragma unroll
-                        for (int e = 0; e < VE; ++e) {
-                            sh = fmaf(xv[e], bh[b][i][e], sh);
-                            sl = fmaf(xv[e], bl[b][i][e], sl);
-                        }
+                        for (int e = 0; e < VE; ++e) sacc = fma((double)xv[e], bd[b][i][e], sacc);
                     }
-                    v[j] = HiLo{sh, sl};
+                    v[j] = sacc;
                 }
-                seg_reduce<LPR / 2, R, R, HiLo>(v, lane);
+                seg_reduce<LPR / 2, R, R, double>(v, lane);
 #pragma unroll
-                for (int o = 0; o < OWN; ++o) uo[o] = (double)v[o].h + (double)v[o].l;
+                for (int o = 0; o < OWN; ++o) uo[o] = v[o];
             }
             if constexpr (SPLIT_TR) {
                 ub[b] = uo[0];
@@ -747,6 +867,17 @@ struct WaveTile {
 #pragma unroll
                         for (int e = 0; e < VE; ++e)
                             g64[b][i][e] = fma(rs[j], chunk_elem_f64(t.x[j][i], e), g64[b][i][e]);
+            } else if constexpr (G64) {
+#pragma unroll
+                for (int j = 0; j < R; ++j)
+#pragma unroll
+                    for (int i = 0; i < CPL; ++i) {
+                        float xv[VE];
+                        decode_chunk<DT>(t.x[j][i], xv);
+#pragma unroll
+                        for (int e = 0; e < VE; ++e)
+                            g64[b][i][e] = fma(rs[j], (double)xv[e], g64[b][i][e]);
+                    }
             } else {
                 float g32[CPL][VE];
 #pragma unroll
@@ -830,29 +961,53 @@ __device__ __forceinline__ void block_merge(const FgParams& p, const int blk, co
     constexpr int VE = WT::VE;
     constexpr int CPL = WT::CHUNKS;
     const int K1 = p.K + 1;
-    __shared__ double gsh[NB][KT];
+    // Each wave's column totals go to a slice of their own and are added in
+    // wave order after one barrier; when the slices do not fit in 32 KB of
+    // LDS the waves add into one vector in turn, a barrier each (the same
+    // additions in the same order, so the same bits).
+    constexpr bool SLICES = WPB * NB * KT * 8 <= 32768;
+    __shared__ double gsh[SLICES ? WPB : 1][NB][KT];
     __shared__ double fsh[WPB][NB];
     if (wt.lane == 0)
 #pragma unroll
         for (int b = 0; b < NB; ++b) fsh[wave][b] = wt.facc[b];
-    for (int w = 0; w < WPB; ++w) {
-        if (wave == w && wt.seg == 0) {
+    if constexpr (SLICES) {
+        if (wt.seg == 0) {
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int i = 0; i < CPL; ++i)
 #pragma unroll
-                    for (int e = 0; e < VE; ++e) {
-                        const int k = wt.col(i, e);
-                        gsh[b][k] = (w == 0 ? 0.0 : gsh[b][k]) + wt.g64[b][i][e];
-                    }
+                    for (int e = 0; e < VE; ++e) gsh[wave][b][wt.col(i, e)] = wt.g64[b][i][e];
         }
         __syncthreads();
+    } else {
+        for (int w = 0; w < WPB; ++w) {
+            if (wave == w && wt.seg == 0) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                        for (int e = 0; e < VE; ++e) {
+                            const int k = wt.col(i, e);
+                            gsh[0][b][k] = (w == 0 ? 0.0 : gsh[0][b][k]) + wt.g64[b][i][e];
+                        }
+            }
+            __syncthreads();
+        }
     }
     double* part = p.partials + (int64_t)blk * NB * K1;
     for (int b = 0; b < NB; ++b) {
         for (int k = threadIdx.x; k < p.K; k += blockDim.x) {
-            double sacc = gsh[b][k];
+            double sacc;
+            if constexpr (SLICES) {
+                sacc = 0.0;
+#pragma unroll
+                for (int w = 0; w < WPB; ++w) sacc += gsh[w][b][k];
+            } else {
+                sacc = gsh[0][b][k];
+            }
             if constexpr (DT == DT_FP8) sacc *= (double)p.scale[k];
             part[b * K1 + 1 + k] = sacc;
         }
@@ -889,10 +1044,7 @@ __device__ __forceinline__ void fg_pass(const FgParams& p, const int blk) {
 #pragma unroll
             for (int i = 0; i < CPL; ++i)
 #pragma unroll
-                for (int e = 0; e < VE; ++e) {
-                    wt.bh[b][i][e] = wt.bl[b][i][e] = 0.0f;
-                    wt.bd[b][i][e] = 0.0;
-                }
+                for (int e = 0; e < VE; ++e) wt.bd[b][i][e] = 0.0;
         }
     }
     wt.zero_acc();

@@ -44,15 +44,24 @@ namespace glmrt {
 namespace {
 
 constexpr int WPB = 4;
-constexpr int RB = 16;
+
+// Row slots per lane: 16 slots of 16 bytes, or 8 for FP32 (its FP64
+// gradient products keep r in FP64; 8 slots keep two waves per SIMD),
+// divided by the chunks per lane of wide rows.
+template <int DT, int CPL>
+constexpr int rb() {
+    return (DT == glmk::DT_F32 ? 8 : 16) / CPL;
+}
 
 struct BInst {
     const void* fn;
+    int R;
 };
 
 template <int DT, int LPR, int CPL>
 BInst binst() {
-    return BInst{reinterpret_cast<const void*>(&glmk::fg_batched<DT, LPR, CPL, RB, WPB>)};
+    constexpr int R = rb<DT, CPL>();
+    return BInst{reinterpret_cast<const void*>(&glmk::fg_batched<DT, LPR, CPL, R, WPB>), R};
 }
 
 template <int DT>
@@ -71,7 +80,7 @@ BInst bpick(int lpr, int cpl) {
         if (cpl == 2) return binst<DT, 64, 2>();
         if (cpl == 4) return binst<DT, 64, 4>();
     }
-    return BInst{nullptr};
+    return BInst{nullptr, 0};
 }
 
 BInst bpick_any(int dt, int lpr, int cpl) {
@@ -81,7 +90,7 @@ BInst bpick_any(int dt, int lpr, int cpl) {
     case GLM_BF16: return bpick<glmk::DT_BF16>(lpr, cpl);
     case GLM_FP8_E4M3: return bpick<glmk::DT_FP8>(lpr, cpl);
     }
-    return BInst{nullptr};
+    return BInst{nullptr, 0};
 }
 
 struct Schedule {
@@ -345,11 +354,12 @@ glm_status glm_groupset_create(glm_ctx* ctx, const glm_dataset_desc* d, const in
     gs->offsets.assign(offsets, offsets + G + 1);
     gs->lpr = plan.lpr;
     gs->cpl = plan.cpl;
-    gs->R = RB;
+    const BInst bi = bpick_any(d->dtype, plan.lpr, plan.cpl);
+    if (!bi.fn) GLM_FAIL(GLM_EINVAL, "glm_groupset_create: no kernel instance for K = %d", d->K);
+    gs->R = bi.R;
     gs->wpb = WPB;
-    gs->batch_rows = RB * (64 / plan.lpr);
-    gs->fn = bpick_any(d->dtype, plan.lpr, plan.cpl).fn;
-    if (!gs->fn) GLM_FAIL(GLM_EINVAL, "glm_groupset_create: no kernel instance for K = %d", d->K);
+    gs->batch_rows = bi.R * (64 / plan.lpr);
+    gs->fn = bi.fn;
     if (tune)
         st = autotune(gs.get());
     else

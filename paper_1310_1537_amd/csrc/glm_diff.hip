@@ -228,11 +228,11 @@ __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
     __shared__ unsigned s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned prev =
             __hip_atomic_fetch_add(p.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = prev == gridDim.x - 1 ? 1u : 0u;
-        if (s_last) __threadfence();
+        if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (!s_last) return;

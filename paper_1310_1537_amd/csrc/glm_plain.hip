@@ -20,9 +20,11 @@ struct Inst {
 
 template <int DT, int LPR, int CPL>
 Inst inst() {
-    // 16 row slots of 16 bytes per lane per batch (64 VGPRs per tile)
+    // 16 row slots of 16 bytes per lane per batch (64 VGPRs per tile); FP32
+    // takes 8 (its FP64 gradient products keep r in FP64, and with 16 slots
+    // the kernel no longer fits two waves per SIMD)
     constexpr int VE = 16 / glmk::ElemSize<DT>::v;
-    constexpr int RE = 16;
+    constexpr int RE = DT == glmk::DT_F32 ? 8 : 16;
     constexpr int R = RE / CPL > 0 ? RE / CPL : 1;
     return Inst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, R, WPB>), R};
 }

@@ -4,7 +4,12 @@
 // flight on n_streams streams (continuous batching: requests that arrive
 // while passes run are packed into the next free slot).  Data sets are
 // admitted to device memory on first use within an HBM budget, evicting the
-// least recently used idle ones when needed.
+// least recently used idle ones when needed.  Admission is asynchronous: the
+// scheduler only reserves the budget; an admission thread obtains the memory
+// (reusing evicted allocations, or the stream-ordered allocator) and copies
+// the data set on a copy stream of its own (through pinned staging buffers
+// when the source is pageable), so passes over resident data sets keep
+// running while a data set is loaded, and no call synchronises the device.
 //
 // The offload cost of a host-driven call is the reason for this design
 // (Sec. 4.5): one transfer + launch pays for up to NB evaluations.  A small
@@ -48,13 +53,20 @@ struct Result {
     std::vector<double> g;
 };
 
+enum { DS_OUT = 0, DS_LOADING = 1, DS_RESIDENT = 2 };
+
 struct SDataset {
     glm_dataset_desc src;     // as given (host or device pointers)
     bool on_device = false;   // caller-owned device buffers: always resident, never evicted
-    bool resident = false;
+    int state = DS_OUT;       // loading: budget reserved, copy in progress
     glm_dataset_desc dev{};   // device copy in use
     void* mem = nullptr;      // server allocation (host-sourced data sets)
-    size_t bytes = 0;
+    size_t mem_bytes = 0;     // its size
+    size_t bytes = 0;         // budget charge (data_bytes)
+    size_t pass_bytes = 0;    // algorithmic bytes of one pass: N (K size + 1)
+    size_t held = 0;          // budget collected while waiting to be admitted
+    int fresh = 0;            // passes still owed to the requests queued at admission:
+                              // until they ran, the data set is not evicted
     uint64_t last_use = 0;
     int inflight = 0;
     Plan plan;
@@ -87,6 +99,42 @@ struct Slot {
     Scratch scratch;
 };
 
+// Latency record in O(1) memory: counts per bucket of a 2 % geometric grid
+// from 0.1 us to about 10^4 s (quantiles to within one bucket, 2 %), plus
+// the exact sum for the mean.
+struct LatHist {
+    static constexpr int NB = 1300;
+    static constexpr double LO = 0.1, STEP = 1.02;
+    uint64_t cnt[NB] = {};
+    uint64_t n = 0;
+    double sum = 0.0;
+    void add(double us) {
+        int b = us <= LO ? 0 : (int)(std::log(us / LO) / std::log(STEP));
+        b = std::min(std::max(b, 0), NB - 1);
+        cnt[b]++;
+        n++;
+        sum += us;
+    }
+    // the geometric middle of the bucket holding the q-quantile
+    double quantile(double q) const {
+        if (!n) return 0.0;
+        const uint64_t want = std::min(n - 1, (uint64_t)(q * (double)(n - 1))) + 1;
+        uint64_t c = 0;
+        for (int b = 0; b < NB; ++b) {
+            c += cnt[b];
+            if (c >= want) return LO * std::pow(STEP, b + 0.5);
+        }
+        return LO * std::pow(STEP, NB - 0.5);
+    }
+    void clear() { *this = LatHist(); }
+};
+
+// An allocation kept after its data set was evicted, for reuse.
+struct CachedMem {
+    void* p;
+    size_t bytes;
+};
+
 }  // namespace
 }  // namespace glmrt
 
@@ -109,13 +157,30 @@ struct glm_server {
     std::vector<Slot> slots;
     std::vector<hipStream_t> streams;
     uint64_t use_clock = 0;
-    size_t resident_bytes = 0;
+    uint64_t wake = 0;          // bumped by every event the scheduler may wait for
+    size_t resident_bytes = 0;  // budget charge of resident and loading data sets (and
+                                // of what the holder has collected)
+    int64_t holder = -1;        // the data set collecting budget for its admission
+    size_t device_bytes = 0;    // of those, caller-owned device data sets (never evicted)
+    // admission
+    std::thread admit_th;
+    std::condition_variable admit_cv;
+    std::deque<int64_t> admit_q;        // data sets whose copy is to start, in order
+    std::vector<CachedMem> cache;       // evicted allocations kept for reuse
+    size_t cached_bytes = 0;
+    hipStream_t copy_stream = nullptr;
+    unsigned char* stage[2] = {nullptr, nullptr};   // pinned staging for pageable sources
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    hipEvent_t copy_done = nullptr;
+    bool pools = false;         // stream-ordered allocator available
     // statistics
     uint64_t submitted = 0, completed = 0, cancelled = 0, failed = 0;
     uint64_t passes = 0, betas_in_passes = 0, admissions = 0, evictions = 0, launches = 0;
+    uint64_t bytes_streamed = 0, bytes_admitted = 0, bytes_staged = 0;
+    double admit_seconds = 0.0;
     int max_sets = 32;   // data sets per launch at most
     uint64_t hist[9] = {0};
-    std::vector<float> lat_us;   // submit -> completion of finished requests
+    LatHist lat;   // submit -> completion of finished requests
     std::string sched_error;
 };
 
@@ -129,57 +194,237 @@ size_t data_bytes(const glm_dataset_desc& d) {
     return b;
 }
 
-// Frees the server's copy of an idle host-sourced data set.
+size_t pass_bytes(const glm_dataset_desc& d) {
+    return (size_t)d.N * ((size_t)d.K * elem_size(d.dtype) + 1);
+}
+
+// Evicts an idle host-sourced data set: its budget charge is released and
+// its allocation kept for reuse (freeing it here would synchronise the
+// device).  Called with s->mu held.
 void evict(glm_server* s, SDataset& ds) {
-    if (ds.mem) (void)hipFree(ds.mem);
+    if (ds.mem) {
+        s->cache.push_back(CachedMem{ds.mem, ds.mem_bytes});
+        s->cached_bytes += ds.mem_bytes;
+    }
     ds.mem = nullptr;
-    ds.resident = false;
+    ds.mem_bytes = 0;
+    ds.state = DS_OUT;
     s->resident_bytes -= ds.bytes;
     s->evictions++;
 }
 
-// 1: resident now, 0: must wait (budget held by busy data sets), -1: error.
-int admit(glm_server* s, SDataset& ds) {
-    if (ds.resident) return 1;
-    while (s->resident_bytes + ds.bytes > s->cfg.hbm_budget_bytes) {
+// Called with s->mu held.  1: resident; 0: wait; -1: it can never fit
+// (nothing that holds budget beside it could ever be evicted).
+//
+// Admission is first come, first served: one data set at a time (the
+// holder) collects budget, taking free budget and evicting idle host-sourced
+// data sets (those with no request queued first, least recently used first).
+// When that is not enough it keeps what it took and waits: no other data set
+// is admitted and no new pass starts on an evictable one (dispatch checks
+// the holder) until the passes in flight finish and their data sets can be
+// evicted too, so a large data set cannot be starved by smaller ones that
+// keep taking the budget it frees.  A fully reserved data set is queued for
+// the admission thread and counts as just used.  Once loaded it owes passes
+// to the requests queued for it then (fresh): it is not evicted, and takes
+// passes even while a holder waits, until those have run.
+int admit(glm_server* s, int64_t id, SDataset& ds) {
+    if (ds.state == DS_RESIDENT) return 1;
+    if (ds.state == DS_LOADING) return 0;
+    if (s->holder >= 0 && s->holder != id) return 0;
+    const size_t need = ds.bytes - ds.held;
+    size_t free = s->cfg.hbm_budget_bytes > s->resident_bytes
+                      ? (size_t)(s->cfg.hbm_budget_bytes - s->resident_bytes)
+                      : 0;
+    bool busy = false;
+    while (free < need) {
         SDataset* lru = nullptr;
+        bool lru_wanted = true;
+        busy = false;
         for (auto& kv : s->datasets) {
             SDataset& o = kv.second;
-            if (o.resident && !o.on_device && o.inflight == 0 && (!lru || o.last_use < lru->last_use))
+            if (&o == &ds || o.on_device || o.state == DS_OUT) continue;
+            if (o.state == DS_LOADING || o.inflight > 0 || o.fresh > 0) {
+                busy = true;
+                continue;
+            }
+            auto q = s->pending.find(kv.first);
+            const bool wanted = q != s->pending.end() && !q->second.empty();
+            if (!lru || (lru_wanted && !wanted) ||
+                (wanted == lru_wanted && o.last_use < lru->last_use)) {
                 lru = &o;
+                lru_wanted = wanted;
+            }
         }
-        if (!lru) return 0;
+        if (!lru) break;
         evict(s, *lru);
+        free += lru->bytes;
     }
-    const size_t es = elem_size(ds.src.dtype);
-    const size_t xb = (size_t)ds.src.N * ds.src.ldx * es;
-    const size_t xb_al = (xb + 255) / 256 * 256;
-    const size_t yb_al = ((size_t)ds.src.N + 255) / 256 * 256;
-    const size_t sb = ds.src.col_scale ? (size_t)ds.src.K * 4 : 0;
-    void* mem = nullptr;
-    if (hipMalloc(&mem, xb_al + yb_al + sb + 256) != hipSuccess) {
-        s->sched_error = "device allocation for a data set failed";
-        return -1;
+    const size_t take = std::min(free, need);
+    ds.held += take;
+    s->resident_bytes += take;
+    if (ds.held < ds.bytes) {
+        if (!busy) {   // cannot happen when every set fits beside the device-resident ones
+            s->resident_bytes -= ds.held;
+            ds.held = 0;
+            s->holder = -1;
+            return -1;
+        }
+        s->holder = id;
+        return 0;
     }
-    char* base = (char*)mem;
-    ds.dev = ds.src;
-    ds.dev.X = base;
-    ds.dev.y = (const uint8_t*)(base + xb_al);
-    ds.dev.col_scale = sb ? (const float*)(base + xb_al + yb_al) : nullptr;
-    hipError_t e = hipSuccess;
-    if (xb) e = hipMemcpy((void*)ds.dev.X, ds.src.X, xb, hipMemcpyHostToDevice);
-    if (e == hipSuccess && ds.src.N) e = hipMemcpy((void*)ds.dev.y, ds.src.y, ds.src.N, hipMemcpyHostToDevice);
-    if (e == hipSuccess && sb) e = hipMemcpy((void*)ds.dev.col_scale, ds.src.col_scale, sb, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(mem);
-        s->sched_error = hipGetErrorString(e);
-        return -1;
+    ds.held = 0;   // now the data set's own charge in resident_bytes
+    s->holder = -1;
+    ds.last_use = ++s->use_clock;
+    ds.state = DS_LOADING;
+    s->admit_q.push_back(id);
+    s->admit_cv.notify_all();
+    return 0;
+}
+
+// Copies n bytes from a host source to device memory on the copy stream:
+// directly when the source is pinned, else through the two pinned staging
+// buffers (a buffer is refilled once its previous copy has finished).
+constexpr size_t kStageBytes = size_t(32) << 20;
+
+hipError_t copy_in(glm_server* s, void* dst, const void* src, size_t n, int& turn,
+                   size_t& staged) {
+    if (!n) return hipSuccess;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, src);
+    if (e != hipSuccess) (void)hipGetLastError();   // pageable memory on some runtimes
+    const bool pinned = e == hipSuccess && attr.type == hipMemoryTypeHost;
+    if (pinned) return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s->copy_stream);
+    staged += n;
+    for (size_t off = 0; off < n; off += kStageBytes) {
+        const size_t len = std::min(kStageBytes, n - off);
+        const int b = turn++ & 1;
+        e = hipEventSynchronize(s->stage_ev[b]);
+        if (e != hipSuccess) return e;
+        std::memcpy(s->stage[b], (const char*)src + off, len);
+        e = hipMemcpyAsync((char*)dst + off, s->stage[b], len, hipMemcpyHostToDevice, s->copy_stream);
+        if (e != hipSuccess) return e;
+        e = hipEventRecord(s->stage_ev[b], s->copy_stream);
+        if (e != hipSuccess) return e;
     }
-    ds.mem = mem;
-    ds.resident = true;
-    s->resident_bytes += ds.bytes;
-    s->admissions++;
-    return 1;
+    return hipSuccess;
+}
+
+// Fails every queued request of a data set (with s->mu held).
+void fail_queue(glm_server* s, int64_t dsid) {
+    auto& q = s->pending[dsid];
+    for (Request& r : q) {
+        s->results[r.ticket].state = R_FAILED;
+        s->failed++;
+    }
+    s->queued -= q.size();
+    q.clear();
+    s->cv.notify_all();
+}
+
+// The admission thread: for each data set queued by admit(), takes an
+// evicted allocation that fits (at most twice the size), else releases
+// cached allocations beyond the budget and allocates on the copy stream;
+// copies X, y and the FP8 scales; waits for the copy; marks the data set
+// resident and wakes the scheduler.
+void admitter(glm_server* s) {
+    (void)hipSetDevice(s->ctx->device);
+    int turn = 0;
+    while (true) {
+        int64_t id;
+        SDataset* ds;
+        void* mem = nullptr;
+        size_t mem_bytes = 0, need = 0;
+        std::vector<CachedMem> release;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->admit_cv.wait(lk, [&] { return s->stop || !s->admit_q.empty(); });
+            if (s->stop) return;   // queued requests are cancelled by the shutdown
+            id = s->admit_q.front();
+            s->admit_q.pop_front();
+            ds = &s->datasets[id];
+            const size_t es = elem_size(ds->src.dtype);
+            const size_t xb_al = ((size_t)ds->src.N * ds->src.ldx * es + 255) / 256 * 256;
+            const size_t yb_al = ((size_t)ds->src.N + 255) / 256 * 256;
+            const size_t sb = ds->src.col_scale ? (size_t)ds->src.K * 4 : 0;
+            need = xb_al + yb_al + sb + 256;
+            int best = -1;
+            for (int i = 0; i < (int)s->cache.size(); ++i) {
+                const size_t b = s->cache[i].bytes;
+                if (b >= need && b <= 2 * need && (best < 0 || b < s->cache[best].bytes)) best = i;
+            }
+            if (best >= 0) {
+                mem = s->cache[best].p;
+                mem_bytes = s->cache[best].bytes;
+                s->cached_bytes -= mem_bytes;
+                s->cache.erase(s->cache.begin() + best);
+            }
+            // keep what the server holds (resident, loading and cached) within the budget
+            while (!s->cache.empty() &&
+                   s->resident_bytes + s->cached_bytes > s->cfg.hbm_budget_bytes) {
+                release.push_back(s->cache.back());
+                s->cached_bytes -= s->cache.back().bytes;
+                s->cache.pop_back();
+            }
+        }
+        const auto t0 = Clock::now();
+        size_t staged = 0;
+        hipError_t e = hipSuccess;
+        for (const CachedMem& c : release)
+            if (e == hipSuccess) e = s->pools ? hipFreeAsync(c.p, s->copy_stream) : hipFree(c.p);
+        if (e == hipSuccess && !mem) {
+            e = s->pools ? hipMallocAsync(&mem, need, s->copy_stream) : hipMalloc(&mem, need);
+            mem_bytes = need;
+            if (e != hipSuccess) mem = nullptr;
+        }
+        glm_dataset_desc dev = ds->src;
+        if (e == hipSuccess) {
+            const size_t es = elem_size(ds->src.dtype);
+            const size_t xb = (size_t)ds->src.N * ds->src.ldx * es;
+            const size_t xb_al = (xb + 255) / 256 * 256;
+            const size_t yb_al = ((size_t)ds->src.N + 255) / 256 * 256;
+            const size_t sb = ds->src.col_scale ? (size_t)ds->src.K * 4 : 0;
+            char* base = (char*)mem;
+            dev.X = base;
+            dev.y = (const uint8_t*)(base + xb_al);
+            dev.col_scale = sb ? (const float*)(base + xb_al + yb_al) : nullptr;
+            e = copy_in(s, (void*)dev.X, ds->src.X, xb, turn, staged);
+            if (e == hipSuccess)
+                e = copy_in(s, (void*)dev.y, ds->src.y, (size_t)ds->src.N, turn, staged);
+            if (e == hipSuccess && sb)
+                e = copy_in(s, (void*)dev.col_scale, ds->src.col_scale, sb, turn, staged);
+            if (e == hipSuccess) e = hipEventRecord(s->copy_done, s->copy_stream);
+            if (e == hipSuccess) e = hipEventSynchronize(s->copy_done);
+        }
+        const double sec = std::chrono::duration<double>(Clock::now() - t0).count();
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (e != hipSuccess) {
+            if (mem) {
+                s->cache.push_back(CachedMem{mem, mem_bytes});
+                s->cached_bytes += mem_bytes;
+            }
+            s->resident_bytes -= ds->bytes;
+            ds->state = DS_OUT;
+            s->sched_error = std::string("data set admission failed: ") + hipGetErrorString(e);
+            fail_queue(s, id);
+        } else {
+            ds->dev = dev;
+            ds->mem = mem;
+            ds->mem_bytes = mem_bytes;
+            ds->state = DS_RESIDENT;
+            {
+                const int NB = ds->mi.fn ? ds->mi.NB : 1;
+                auto q = s->pending.find(id);
+                const size_t nq = q == s->pending.end() ? 0 : q->second.size();
+                ds->fresh = (int)((nq + NB - 1) / NB);   // 0 if nothing waits for it
+            }
+            s->admissions++;
+            s->bytes_admitted += ds->bytes;
+            s->bytes_staged += staged;
+            s->admit_seconds += sec;
+        }
+        s->wake++;
+        s->cv.notify_all();
+    }
 }
 
 // Grows the slot's staging areas and scratch to at least the given sizes
@@ -241,8 +486,7 @@ bool reap(glm_server* s) {
                 r.state = R_DONE;
                 r.f = o[(size_t)i * (j.K + 1)];
                 r.g.assign(o + (size_t)i * (j.K + 1) + 1, o + (size_t)(i + 1) * (j.K + 1));
-                s->lat_us.push_back(
-                    (float)std::chrono::duration<double, std::micro>(now - sl.t_submit[t]).count());
+                s->lat.add(std::chrono::duration<double, std::micro>(now - sl.t_submit[t]).count());
             }
             s->datasets[j.ds].inflight--;
         }
@@ -252,18 +496,6 @@ bool reap(glm_server* s) {
     }
     if (any) s->cv.notify_all();
     return any;
-}
-
-// Fails every queued request of a data set (its admission failed).
-void fail_queue(glm_server* s, int64_t dsid) {
-    auto& q = s->pending[dsid];
-    for (Request& r : q) {
-        s->results[r.ticket].state = R_FAILED;
-        s->failed++;
-    }
-    s->queued -= q.size();
-    q.clear();
-    s->cv.notify_all();
 }
 
 // A data set chosen for a launch with the requests it takes.
@@ -300,8 +532,13 @@ bool dispatch(glm_server* s) {
             SDataset& ds = s->datasets[h.second];
             if (!picks.empty() && !fleet) break;
             if (!picks.empty() && ds.mi.fleet != fleet) continue;
-            const int a = admit(s, ds);
+            // while a data set waits for budget, evictable ones take no new
+            // passes (their passes in flight finish and free it)
+            if (s->holder >= 0 && !ds.on_device && ds.state == DS_RESIDENT && ds.fresh == 0)
+                continue;
+            const int a = admit(s, h.second, ds);
             if (a < 0) {
+                s->sched_error = "data set can never fit the HBM budget beside the device-resident ones";
                 fail_queue(s, h.second);
                 failed = true;
                 continue;
@@ -315,6 +552,7 @@ bool dispatch(glm_server* s) {
                 q.pop_front();
             }
             s->queued -= pk.reqs.size();
+            if (ds.fresh > 0) ds.fresh--;
             ds.inflight++;   // also keeps it from being evicted by a later admission
             ds.last_use = ++s->use_clock;
             if (picks.empty()) fleet = s->max_sets > 1 ? ds.mi.fleet : nullptr;
@@ -435,6 +673,7 @@ bool dispatch(glm_server* s) {
             sl->t_submit.push_back(r.t_submit);
         }
         s->passes++;
+        s->bytes_streamed += pk.ds->pass_bytes;
         s->betas_in_passes += nb;
         s->hist[std::min(nb, 8)]++;
     }
@@ -444,7 +683,12 @@ bool dispatch(glm_server* s) {
 
 void scheduler(glm_server* s) {
     (void)hipSetDevice(s->ctx->device);
+    uint64_t seen = 0;
     while (true) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            seen = s->wake;
+        }
         bool progress = reap(s);
         while (dispatch(s)) progress = true;
         bool busy = false;
@@ -452,11 +696,11 @@ void scheduler(glm_server* s) {
         std::unique_lock<std::mutex> lk(s->mu);
         if (s->stop && !busy && (s->queued == 0 || !s->accepting)) break;
         if (!progress) {
-            if (busy)
+            if (busy)   // poll the slots' events
                 s->cv.wait_for(lk, std::chrono::microseconds(5));
-            else
+            else        // wait for a request, an admitted data set or the stop
                 s->cv.wait_for(lk, std::chrono::milliseconds(2),
-                               [&] { return s->stop || s->queued > 0; });
+                               [&] { return s->stop || s->wake != seen; });
         }
     }
 }
@@ -488,8 +732,18 @@ glm_status glm_server_create(glm_ctx* ctx, const glm_server_config* cfg, glm_ser
         s->slots[i].stream = s->streams[i % cfg->n_streams];
         GLM_HIP_CHECK(hipEventCreateWithFlags(&s->slots[i].done, hipEventDisableTiming));
     }
+    int pools = 0;
+    GLM_HIP_CHECK(hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, ctx->device));
+    s->pools = pools != 0;
+    GLM_HIP_CHECK(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
+    GLM_HIP_CHECK(hipEventCreateWithFlags(&s->copy_done, hipEventDisableTiming));
+    for (int b = 0; b < 2; ++b) {
+        GLM_HIP_CHECK(hipHostMalloc((void**)&s->stage[b], kStageBytes));
+        GLM_HIP_CHECK(hipEventCreateWithFlags(&s->stage_ev[b], hipEventDisableTiming));
+    }
     glm_server* raw = s.get();
     s->th = std::thread(scheduler, raw);
+    s->admit_th = std::thread(admitter, raw);
     *out = s.release();
     return GLM_OK;
 }
@@ -504,10 +758,16 @@ glm_status glm_server_add_dataset(glm_server* s, const glm_dataset_desc* d, int3
     ds.src = *d;
     ds.on_device = on_device != 0;
     ds.bytes = data_bytes(*d);
+    ds.pass_bytes = pass_bytes(*d);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (ds.bytes > s->cfg.hbm_budget_bytes ||
-        (ds.on_device && s->resident_bytes + ds.bytes > s->cfg.hbm_budget_bytes))
-        GLM_FAIL(GLM_EBUDGET, "glm_server_add_dataset: %zu bytes exceed the HBM budget", ds.bytes);
+    // Device-resident data sets are never evicted, so every data set must fit
+    // beside all of them: then admission can always make room by evicting
+    // idle host-sourced ones.
+    if (s->device_bytes + ds.bytes > s->cfg.hbm_budget_bytes)
+        GLM_FAIL(GLM_EBUDGET,
+                 "glm_server_add_dataset: %zu bytes do not fit the HBM budget of %llu beside the "
+                 "%zu bytes of device-resident data sets",
+                 ds.bytes, (unsigned long long)s->cfg.hbm_budget_bytes, s->device_bytes);
     // plan on the device layout (16-byte alignment of the server's copy holds)
     glm_dataset_desc probe = *d;
     if (!ds.on_device) probe.X = nullptr;
@@ -516,8 +776,9 @@ glm_status glm_server_add_dataset(glm_server* s, const glm_dataset_desc* d, int3
     ds.mi = multi_instance(d->dtype, ds.plan.lpr, ds.plan.cpl, s->cfg.max_beta_per_pass);
     if (ds.on_device) {
         ds.dev = *d;
-        ds.resident = true;
+        ds.state = DS_RESIDENT;
         s->resident_bytes += ds.bytes;
+        s->device_bytes += ds.bytes;
     }
     const int64_t id = s->next_ds++;
     s->datasets[id] = ds;
@@ -552,6 +813,7 @@ glm_status glm_server_submit(glm_server* s, glm_dataset_id ds, const double* bet
         s->pending[ds].push_back(std::move(r));
         s->queued++;
         s->submitted++;
+        s->wake++;
     }
     s->cv.notify_all();
     return GLM_OK;
@@ -589,6 +851,7 @@ glm_status glm_server_submit_many(glm_server* s, int32_t n, const glm_dataset_id
         }
         s->queued += n;
         s->submitted += n;
+        s->wake++;
     }
     s->cv.notify_all();
     return GLM_OK;
@@ -676,23 +939,20 @@ glm_status glm_server_stats(glm_server* s, glm_server_metrics* out) {
     out->evictions = s->evictions;
     out->resident_bytes = s->resident_bytes;
     int nres = 0;
-    for (auto& kv : s->datasets) nres += kv.second.resident;
+    for (auto& kv : s->datasets) nres += kv.second.state == DS_RESIDENT;
     out->resident_datasets = nres;
     out->queue_depth = (int32_t)s->queued;
     for (int i = 0; i < 9; ++i) out->pass_width_hist[i] = s->hist[i];
-    if (!s->lat_us.empty()) {
-        std::vector<float> v = s->lat_us;
-        auto pct = [&](double q) {
-            const size_t k = std::min(v.size() - 1, (size_t)(q * (v.size() - 1)));
-            std::nth_element(v.begin(), v.begin() + k, v.end());
-            return (double)v[k];
-        };
-        out->latency_p50_us = pct(0.50);
-        out->latency_p99_us = pct(0.99);
-        double sum = 0;
-        for (float x : s->lat_us) sum += x;
-        out->latency_mean_us = sum / s->lat_us.size();
+    if (s->lat.n) {
+        out->latency_p50_us = s->lat.quantile(0.50);
+        out->latency_p99_us = s->lat.quantile(0.99);
+        out->latency_mean_us = s->lat.sum / (double)s->lat.n;
     }
+    out->bytes_streamed = s->bytes_streamed;
+    out->bytes_admitted = s->bytes_admitted;
+    out->admit_seconds = s->admit_seconds;
+    out->cached_bytes = s->cached_bytes;
+    out->bytes_staged = s->bytes_staged;
     return GLM_OK;
 }
 
@@ -702,8 +962,10 @@ glm_status glm_server_reset_stats(glm_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->submitted = s->completed = s->cancelled = s->failed = 0;
     s->passes = s->betas_in_passes = s->admissions = s->evictions = s->launches = 0;
+    s->bytes_streamed = s->bytes_admitted = s->bytes_staged = 0;
+    s->admit_seconds = 0.0;
     std::memset(s->hist, 0, sizeof(s->hist));
-    s->lat_us.clear();
+    s->lat.clear();
     return GLM_OK;
 }
 
@@ -722,9 +984,12 @@ glm_status glm_server_shutdown(glm_server* s) {
         }
         s->queued = 0;
         s->stop = true;
+        s->wake++;
     }
     s->cv.notify_all();
+    s->admit_cv.notify_all();
     if (s->th.joinable()) s->th.join();
+    if (s->admit_th.joinable()) s->admit_th.join();
     return GLM_OK;
 }
 
@@ -742,8 +1007,25 @@ glm_status glm_server_destroy(glm_server* s) {
         if (sl.scratch.base) (void)hipFree(sl.scratch.base);
     }
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-    for (auto& kv : s->datasets)
-        if (kv.second.mem) (void)hipFree(kv.second.mem);
+    if (s->copy_stream) {
+        (void)hipStreamSynchronize(s->copy_stream);
+        auto release = [&](void* p) {
+            if (s->pools)
+                (void)hipFreeAsync(p, s->copy_stream);
+            else
+                (void)hipFree(p);
+        };
+        for (auto& kv : s->datasets)
+            if (kv.second.mem) release(kv.second.mem);
+        for (const CachedMem& c : s->cache) release(c.p);
+        (void)hipStreamSynchronize(s->copy_stream);
+        (void)hipStreamDestroy(s->copy_stream);
+    }
+    for (int b = 0; b < 2; ++b) {
+        if (s->stage[b]) (void)hipHostFree(s->stage[b]);
+        if (s->stage_ev[b]) (void)hipEventDestroy(s->stage_ev[b]);
+    }
+    if (s->copy_done) (void)hipEventDestroy(s->copy_done);
     delete s;
     return GLM_OK;
 }

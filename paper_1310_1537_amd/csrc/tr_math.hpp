@@ -11,7 +11,12 @@
 //                s = (z - 1) / (z + 1), |s| <= 0.1716, by the odd series
 //                2 (s + s^3/3 + ... + s^21/21) (next term < 2^-58 relative).
 //
-// Both are within a few units in the last place of the correctly rounded
+//   log(x):      for positive normal x: x = 2^m z with z in [sqrt(1/2),
+//                sqrt(2)) (z - 1 exact), log z = 2 atanh((z - 1) / (z + 1)) by
+//                the same series, and m ln2 added with the split ln2 of exp;
+//                near x = 1 (m = 0) the result keeps its relative accuracy.
+//
+// All are within a few units in the last place of the correctly rounded
 // value; NaN in gives NaN out.
 #pragma once
 
@@ -43,11 +48,8 @@ __device__ __forceinline__ double exp_f64(double x) {
     return ldexp(p, (int)k);
 }
 
-// log(1 + e) for e in [0, 1].
-__device__ __forceinline__ double log1p_unit(double e) {
-    const bool up = e > 0.41421356237309504880;                 // sqrt(2) - 1
-    const double zm1 = up ? (e - 1.0) * 0.5 : e;                // z - 1
-    const double zp1 = up ? (e + 3.0) * 0.5 : e + 2.0;          // z + 1
+// 2 atanh(zm1 / zp1) = log z for z = 1 + zm1 = zp1 - 1 in [sqrt(1/2), sqrt(2)).
+__device__ __forceinline__ double log_series(double zm1, double zp1) {
     const double s = zm1 / zp1;
     const double s2 = s * s;
     double q = 1.0 / 21.0;
@@ -61,8 +63,30 @@ __device__ __forceinline__ double log1p_unit(double e) {
     q = fma(q, s2, 1.0 / 5.0);
     q = fma(q, s2, 1.0 / 3.0);
     const double s3 = s * s2;
-    const double at = fma(2.0 * s3, q, 2.0 * s);                // 2 atanh(s)
+    return fma(2.0 * s3, q, 2.0 * s);                           // 2 atanh(s)
+}
+
+// log(1 + e) for e in [0, 1].
+__device__ __forceinline__ double log1p_unit(double e) {
+    const bool up = e > 0.41421356237309504880;                 // sqrt(2) - 1
+    const double zm1 = up ? (e - 1.0) * 0.5 : e;                // z - 1
+    const double zp1 = up ? (e + 3.0) * 0.5 : e + 2.0;          // z + 1
+    const double at = log_series(zm1, zp1);
     return up ? at + 6.93147180559945309417e-01 : at;           // + m ln2
+}
+
+// log(x) for positive normal x (the random-number transforms need it on
+// (0, 1)).
+__device__ __forceinline__ double log_f64(double x) {
+    int ex = 0;
+    double z = frexp(x, &ex);                                   // x = z 2^ex, z in [1/2, 1)
+    if (z < 0.70710678118654752440) {                           // sqrt(1/2)
+        z *= 2.0;
+        --ex;
+    }
+    const double m = (double)ex;
+    const double lz = log_series(z - 1.0, z + 1.0);             // z - 1 exact
+    return fma(m, 6.93147180369123816490e-01, fma(m, 1.90821492927058770002e-10, lz));
 }
 
 }  // namespace glmk

@@ -64,7 +64,10 @@ class glm_server_stats_t(ctypes.Structure):
                 ("resident_bytes", ctypes.c_uint64), ("resident_datasets", ctypes.c_int32),
                 ("queue_depth", ctypes.c_int32), ("pass_width_hist", ctypes.c_uint64 * 9),
                 ("latency_p50_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
-                ("latency_mean_us", ctypes.c_double), ("launches", ctypes.c_uint64)]
+                ("latency_mean_us", ctypes.c_double), ("launches", ctypes.c_uint64),
+                ("bytes_streamed", ctypes.c_uint64), ("bytes_admitted", ctypes.c_uint64),
+                ("admit_seconds", ctypes.c_double), ("cached_bytes", ctypes.c_uint64),
+                ("bytes_staged", ctypes.c_uint64)]
 
 
 class glm_colset_desc(ctypes.Structure):
@@ -117,6 +120,10 @@ _SIGS = {
     "glm_diff_logpost": [_P, _I64, _P, _P, _I32, _P, _I32, ctypes.POINTER(glm_prior), _P, _P],
     "glm_diff_commit": [_P, _I64, _P, _P, _I32, _P, _P],
     "glm_mh_run": [_P, _I64, _P, _P, _P, _P, _I32, ctypes.POINTER(glm_prior), _P, _P, _P],
+    "glm_hmc_run": [_P, _I64, _P, _P, _I32, _I32, _D, ctypes.c_uint64, ctypes.c_uint64,
+                    ctypes.c_uint32, ctypes.POINTER(glm_prior), _P, _P, _P],
+    "glm_rng_fill": [_P, _I32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                     ctypes.c_uint64, _I64, _D, _P, _P],
     "glm_logpost_grad_hess": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P, _P],
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_probe_read_bandwidth": [_P, _P, _I64, _I32, _I32, ctypes.POINTER(_D)],
@@ -325,6 +332,27 @@ def glm_mh_run(ctx: int, ds: int, beta, fg, incs, logu, n_steps: int, prior: glm
     """Random-walk Metropolis on the device (all arguments device tensors)."""
     _check(_lib.glm_mh_run(ctx, ds, _ptr(beta), _ptr(fg), _ptr(incs), _ptr(logu), n_steps,
                            ctypes.byref(prior), _ptr(accepted), _ptr(f_trace), _stream(stream)))
+
+
+def glm_hmc_run(ctx: int, ds: int, beta, fg, n_iter: int, n_leap: int, eps: float, seed: int,
+                chain: int, prior: glm_prior, accepted=None, f_trace=None, stream=None,
+                iter0: int = 0) -> None:
+    """Hamiltonian Monte Carlo on the device (beta, fg, accepted, f_trace:
+    device tensors)."""
+    _check(_lib.glm_hmc_run(ctx, ds, _ptr(beta), _ptr(fg), n_iter, n_leap, float(eps), int(seed),
+                            int(chain), int(iter0), ctypes.byref(prior), _ptr(accepted),
+                            _ptr(f_trace), _stream(stream)))
+
+
+GLM_RNG_UNIFORM, GLM_RNG_NORMAL, GLM_RNG_LOG_UNIFORM = 1, 2, 3
+
+
+def glm_rng_fill(ctx: int, kind: int, seed: int, chain: int, stream_id: int, offset: int, n: int,
+                 out, scale: float = 1.0, stream=None) -> None:
+    """Values offset .. offset + n - 1 of a counter-based stream into the
+    device tensor out (float64)."""
+    _check(_lib.glm_rng_fill(ctx, kind, int(seed), int(chain), int(stream_id), int(offset), n,
+                             float(scale), _ptr(out), _stream(stream)))
 
 
 # ---------------------------------------------------------------- batched

@@ -7,24 +7,25 @@ read as 16-byte chunks of VE = 16 / size values; NC = ceil(K / VE) chunks
 are spread over LPR = min(64, pow2ceil(NC)) lanes, CPL = 1 chunk per lane up
 to 64 chunks, else pow2ceil(NC / 64).
 
-  u_n  FP32/BF16/FP8 storage, vector ALU: beta is split into two FP32 parts
-       (hi + lo); each lane adds its CPL * VE products into an FP32 chain
-       (one rounding per FMA), then log2(LPR) butterfly additions in FP32
-       combine the lanes, and hi and lo are added in FP64.  A product therefore
-       meets at most m = CPL * VE + log2(LPR) + 1 roundings of unit 2^-24:
-       |du_n| <= gamma_m A_n with A_n = sum_k |x_nk beta_k|.
+  u_n  vector ALU kernels, every storage type: each stored value is exact
+       in FP64; each lane adds its CPL * VE products into an FP64 FMA chain,
+       then log2(LPR) butterfly additions in FP64 combine the lanes.  A
+       product therefore meets at most m = CPL * VE + log2(LPR) + 1 roundings
+       of unit 2^-53: |du_n| <= gamma_m A_n with A_n = sum_k |x_nk beta_k|
+       (the bound adds K more, for the oracle's own dot product).  FP8: the
+       column scale is folded into beta in FP64 (one rounding of beta).
        BF16 several-beta passes on the matrix cores: beta in four BF16 pieces,
        each accumulated in FP32 over LPR / 4 instructions of 32 exact products;
        the bound takes every one of the 32 + LPR / 4 additions as a rounding
        and the unit as 2^-23 (no assumption on how an instruction rounds
-       inside).  FP64 storage: the same chains in FP64.
+       inside).
   t_n, r_n   FP64 per-row map; r is rounded to FP32 for the products.
   g    FP32 products r_n x_nk summed over at most R = 16 rows, then FP64.
   f    FP64 from each row's t_n; every cross-lane, cross-wave and cross-block
        sum is FP64.
 
-Error of beta's split: beta - hi - lo is at most 2^-48 |beta| (four BF16
-pieces: 2^-31 |beta|); it is the same for every row, so its effect enters
+Error of beta's representation (the FP8 fold: 2^-53 |beta|; four BF16
+pieces: 2^-31 |beta|): it is the same for every row, so its effect enters
 at its worst case.
 
 Two bounds are checked for every f and every g_k, and the result must meet
@@ -88,9 +89,10 @@ def u_model(K: int, storage: str, form: str = "any"):
     BF16 rows of 9 to 64 chunks) or 'any' (the larger of the two where the
     library may pick either)."""
     ve, nc, lpr, cpl = layout(K, storage)
+    valu = (_gamma(cpl * ve + int(math.log2(lpr)) + 1 + K, U64), 1.0,
+            U64 if storage == "fp8" else 0.0)
     if storage == "f64":
-        return _gamma(cpl * ve + int(math.log2(lpr)) + 1 + K, U64), 1.0, 0.0
-    valu = (_gamma(cpl * ve + int(math.log2(lpr)) + 1, U32), 1.0 + 2 * U32, 2.0 ** -47)
+        return valu
     mx_ok = storage == "bf16" and 9 <= nc <= 64
     mx = (_gamma(32 + lpr // 4 + 1, 2.0 ** -23), 1.0 + 2.0 ** -7, 2.0 ** -31)
     if form == "mx":

@@ -172,6 +172,103 @@ def test_server_admission_and_eviction(ctx):
     glm.glm_server_destroy(srv)
 
 
+def _serve_all(srv, ids, sets, reqs):
+    """Submits every (data set index, beta) at once, then waits for each;
+    returns [(f, g)]."""
+    ts = [glm.glm_server_submit(srv, ids[d], b, 0.01) for d, b in reqs]
+    out = []
+    for (d, _), t in zip(reqs, ts):
+        g = np.empty(sets[d][0].shape[1])
+        out.append((glm.glm_server_wait(srv, t, g), g))
+    return out
+
+
+def test_server_churn_under_a_binding_budget(ctx):
+    """Four host-sourced data sets, a budget that holds one and a half of
+    them, 96 requests queued at once in random order: admissions and
+    evictions churn while passes run; every result equals (bitwise) the one
+    a server with room for all four gives, and is within the oracle bound.
+    Afterwards the server holds at most the budget (resident plus evicted
+    allocations kept for reuse)."""
+    sets = [_data(60_000 + 1000 * i, 32, 70 + i) for i in range(4)]
+    one = max(X.shape[0] * (32 * 4 + 1) for X, _, _ in sets)
+    rng = np.random.default_rng(75)
+    reqs = []
+    for _ in range(96):
+        d = int(rng.integers(0, 4))
+        reqs.append((d, sets[d][2] + 0.05 * rng.standard_normal(32)))
+    results = {}
+    for budget in (int(1.5 * one), 1 << 34):
+        srv = _server(ctx, budget=budget, slots=2, streams=2)
+        ids = [glm.glm_server_add_dataset(srv, glm.make_host_desc(X, y)) for X, y, _ in sets]
+        results[budget] = _serve_all(srv, ids, sets, reqs)
+        st = glm.glm_server_stats(srv)
+        assert st["completed"] == 96 and st["failed"] == 0
+        if budget < 1 << 34:
+            # every set was admitted, and holding one and a half of four forces
+            # at least three evictions
+            assert st["evictions"] >= 3 and st["admissions"] >= 4, st
+            assert st["resident_bytes"] + st["cached_bytes"] <= budget, st
+            assert st["bytes_admitted"] >= 4 * 60_000 * 129
+        glm.glm_server_destroy(srv)
+    small, big = results[int(1.5 * one)], results[1 << 34]
+    for (d, beta), (f1, g1), (f2, g2) in zip(reqs, small, big):
+        assert f1 == f2 and np.array_equal(g1, g2)
+    for k in range(0, 96, 12):
+        d, beta = reqs[k]
+        X, y, _ = sets[d]
+        _check(small[k][0], small[k][1], X.astype(np.float64), y, beta, 0.01)
+
+
+def test_server_pinned_and_pageable_sources_agree(ctx):
+    """A data set given in pinned host memory is copied directly, a pageable
+    one through the staging buffers (two chunks of 32 MiB and a tail here):
+    same results, bitwise."""
+    X, y, bt = _data(300_000, 64, 80)   # 76.8 MB of X
+    Xp = torch.from_numpy(X).pin_memory()
+    yp = torch.from_numpy(y).pin_memory()
+    B = _betas(bt, 3, 81)
+    got = []
+    for pinned in (False, True):
+        srv = _server(ctx)
+        if pinned:
+            desc = glm.glm_dataset_desc(Xp.data_ptr(), 64, glm.GLM_F32, None, yp.data_ptr(),
+                                        300_000, 64, 0)
+        else:
+            desc = glm.make_host_desc(X, y)
+        ds = glm.glm_server_add_dataset(srv, desc)
+        r = []
+        for b in B:
+            g = np.empty(64)
+            r.append((glm.glm_server_wait(srv, glm.glm_server_submit(srv, ds, b, 0.01), g), g))
+        got.append(r)
+        glm.glm_server_destroy(srv)
+    for (f1, g1), (f2, g2) in zip(*got):
+        assert f1 == f2 and np.array_equal(g1, g2)
+    _check(got[0][0][0], got[0][0][1], X.astype(np.float64), y, B[0], 0.01)
+
+
+def test_server_host_set_must_fit_beside_device_sets(ctx):
+    """A device-resident data set is never evicted, so a host-sourced one
+    that would not fit beside it is refused at add time (it could never be
+    admitted); one that fits is admitted and served."""
+    X, y, bt = _data(50_000, 32, 90)
+    one = 50_000 * (32 * 4 + 1)
+    Xd, yd = to_dev(X), to_dev(y)
+    srv = _server(ctx, budget=int(1.6 * one))
+    glm.glm_server_add_dataset(srv, glm.make_desc(Xd, yd), on_device=True)
+    Xb, yb, btb = _data(50_000, 32, 91)
+    with pytest.raises(glm.GlmError) as e:
+        glm.glm_server_add_dataset(srv, glm.make_host_desc(Xb, yb))
+    assert e.value.status == glm.GLM_EBUDGET
+    Xs, ys, bts = _data(20_000, 32, 92)
+    ds = glm.glm_server_add_dataset(srv, glm.make_host_desc(Xs, ys))
+    g = np.empty(32)
+    f = glm.glm_server_wait(srv, glm.glm_server_submit(srv, ds, bts, 0.01), g)
+    _check(f, g, Xs.astype(np.float64), ys, bts, 0.01)
+    glm.glm_server_destroy(srv)
+
+
 def test_server_budget_and_unknown_ids(ctx):
     X, y, _ = _data(1000, 8, 50)
     srv = _server(ctx, budget=1000)
