@@ -166,12 +166,12 @@ __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) acc[j] = 0.0;
 
+    // (a guarded body rather than an early exit, so that the loop unrolls and
+    // d and acc stay in registers)
     auto add_row = [&](double x, double un, unsigned yb) {
 #pragma unroll
-        for (int j = 0; j < DMAX; ++j) {
-            if (j >= nd) break;
-            acc[j] += row_term(fma(d[j], x, un), yb, fam);
-        }
+        for (int j = 0; j < DMAX; ++j)
+            if (j < nd) acc[j] += row_term(fma(d[j], x, un), yb, fam);
     };
 
     const int64_t gtid = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -212,10 +212,12 @@ __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < DMAX; ++j) {
-        if (j >= nd) break;
-        double v = acc[j];
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) s_w[wave][j] = v;
+        if (j < nd) {
+            double v = acc[j];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) s_w[wave][j] = v;
+        }
     }
     __syncthreads();
     if (threadIdx.x < nd) {
