@@ -125,7 +125,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
                         double v = wt.g64[0][i][e];
                         if constexpr (DT == DT_FP8) v *= (double)p.scale[k];
                         if (dst) {
-                            dst[1 + k] = v;
+                            publish(dst + 1 + k, v);
                         } else {
                             const double d = beta[k] - (mn ? mn[k] : 0.0);
                             pf += d * d;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
                     }
         }
         if (dst) {
-            if (wt.lane == 0) dst[0] = wt.facc[0];
+            if (wt.lane == 0) publish(dst, wt.facc[0]);
         } else {
             for (int d = 1; d < LPR; d <<= 1) pf += __shfl_xor(pf, d, 64);
             if (wt.lane == 0) o[0] = wt.facc[0] - 0.5 * p.prec * pf;
@@ -157,15 +157,16 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
 
     // Split groups: once every wave of this block is done, the block takes
     // one ticket per split group it holds tiles of; the block completing a
-    // group's count adds that group's tile partials in tile order.  One
-    // release fence per block (not per tile) publishes the partials.
+    // group's count adds that group's tile partials in tile order.  The
+    // partials are published (written through to memory, read coherently), so
+    // the tickets need no fences.
     const int q0 = p.block_groups_ptr[blockIdx.x];
     const int q1 = p.block_groups_ptr[blockIdx.x + 1];
     if (q0 == q1) return;
-    // The barrier orders every wave's partial stores before wave 0's
-    // agent-scope release fence; the tickets themselves can then be relaxed.
+    // Every thread's partial stores complete before the barrier, and the
+    // barrier before wave 0's tickets.
+    publish_wait();
     __syncthreads();
-    if (wave == 0) release_agent();
     __shared__ unsigned s_win[NT];
     for (int qb = q0; qb < q1; qb += NT) {
         if (wave == 0) {
@@ -175,7 +176,6 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
                                                              __HIP_MEMORY_SCOPE_AGENT);
                 s_win[qq - qb] = prev == (unsigned)(p.group_blocks[g] - 1) ? 1u : 0u;
             }
-            acquire_agent();   // tiles published by other blocks
         }
         __syncthreads();
         // The won groups are spread over the waves (entry j to wave

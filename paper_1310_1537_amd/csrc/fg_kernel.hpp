@@ -45,6 +45,7 @@
 
 #include <type_traits>
 
+#include "publish.hpp"
 #include "rng.hpp"
 #include "tr_math.hpp"
 
@@ -286,15 +287,16 @@ __device__ __forceinline__ double tr_weight(double u, int fam) {
 
 // ------------------------------------------------------------ finalisation
 
-// sum_{t < n} a[t * stride] in index order, with 16 loads in flight: the
-// loads of a block are independent, the additions keep the fixed order
-// (padding adds +0.0, which leaves any sum but -0.0 unchanged).
+// sum_{t < n} a[t * stride] of published data in index order, with 16 loads
+// in flight: the loads of a block are independent, the additions keep the
+// fixed order (padding adds +0.0, which leaves any sum but -0.0 unchanged).
 __device__ __forceinline__ double ordered_sum(const double* a, int n, int64_t stride) {
     double s = 0.0;
     for (int t = 0; t < n; t += 16) {
         double v[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = t + j < n ? a[(int64_t)(t + j) * stride] : 0.0;
+        for (int j = 0; j < 16; ++j)
+            v[j] = t + j < n ? fetch_published(a + (int64_t)(t + j) * stride) : 0.0;
 #pragma unroll
         for (int j = 0; j < 16; ++j) s += v[j];
     }
@@ -304,7 +306,7 @@ __device__ __forceinline__ double ordered_sum(const double* a, int n, int64_t st
 // Buffer descriptor word 3 for raw (untyped) buffers on gfx9-class GPUs.
 constexpr int kRsrcWord3 = 0x00020000;
 
-// The same sums for the Q entries idx0 + q * step (q < Q) that are below lim
+// The same sums (of published data) for the Q entries idx0 + q * step (q < Q) that are below lim
 // (the others give 0), with the loads of all Q issued before any addition:
 // one memory latency for Q entries instead of Q.  The loads go through a
 // buffer descriptor spanning the n x stride doubles, so the surplus ones
@@ -318,7 +320,7 @@ __device__ __forceinline__ void ordered_sums(const double* a, int n, int64_t str
         (void*)a, 0, (int)((int64_t)n * stride * 8), kRsrcWord3);
     auto load = [&](int idx, int t) {
         const uint32_t off = idx < lim ? (uint32_t)(idx + (int64_t)t * stride) * 8u : 0x80000000u;
-        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kLoadPublished);
         return __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
     };
     if (n == 1) {   // a single partial (one block, or one group)
@@ -338,6 +340,49 @@ __device__ __forceinline__ void ordered_sums(const double* a, int n, int64_t str
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int j = 0; j < 16; ++j) out[q] += v[q][j];
+    }
+}
+
+// The sums over n published partials (stride doubles apart) of the E entries
+// idx < E, for all NT threads of a block; emit(idx, sum) is called once per
+// entry by one thread (entry idx < NT by thread idx).  When the entries
+// leave threads idle and n needs more than one round of loads, the partials
+// are cut into C contiguous chunks, one thread per (chunk, entry) adds its
+// chunk in order and the chunk sums are added in chunk order through LDS:
+// fewer dependent load rounds, and an order fixed by (n, E, NT), so repeated
+// calls agree bitwise.  Otherwise one entry per thread, or four per thread
+// and round when E > NT.
+template <int NT, typename Emit>
+__device__ __forceinline__ void block_sums(const double* a, int n, int64_t stride, int E,
+                                           Emit&& emit) {
+    const int C = min(NT / max(E, 1), (n + 15) / 16);
+    if (C >= 2) {
+        __shared__ double s_chunk[NT];
+        const int t = threadIdx.x, c = t / E, e = t - c * E;
+        if (c < C) {
+            const int t0 = c * n / C, t1 = (c + 1) * n / C;
+            double v[1];
+            ordered_sums<1>(a + (int64_t)t0 * stride, t1 - t0, stride, e, 0, E, v);
+            s_chunk[t] = v[0];
+        }
+        __syncthreads();
+        if (t < E) {
+            double sum = 0.0;
+            for (int cc = 0; cc < C; ++cc) sum += s_chunk[cc * E + t];
+            emit(t, sum);
+        }
+    } else if (E <= NT) {
+        double v[1];
+        ordered_sums<1>(a, n, stride, threadIdx.x, NT, E, v);
+        if ((int)threadIdx.x < E) emit((int)threadIdx.x, v[0]);
+    } else {
+        for (int i0 = threadIdx.x; i0 < E; i0 += 4 * NT) {
+            double v[4];
+            ordered_sums<4>(a, n, stride, i0, NT, E, v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i0 + q * NT < E) emit(i0 + q * NT, v[q]);
+        }
     }
 }
 
@@ -476,18 +521,13 @@ __device__ __forceinline__ void chain_step(const ChainParams& c, const double* f
     }
 }
 
-// Agent-scope release and acquire fences.  Across the blocks of a launch the
-// merge publishes partials with a release before a relaxed ticket increment,
-// and only the block that completes a count acquires before reading the
-// others' partials (a full fence on both sides would also invalidate the L2
-// of every finishing block and write it back twice).
-__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-
-// Called by every thread of every block after the block has written its
+// Called by every thread of every block after the block has published its
 // partial (NB x (1 + K) doubles at partials + blk * NB * (1 + K), blk being
 // the block's index among the p.nblocks blocks of this evaluation).  NT is
-// the block size (a power of two).
+// the block size (a power of two).  One group of blocks: the block completing
+// the count adds the block partials directly; several: the last block of each
+// group adds its group's partials, and the last group's finisher adds the
+// group sums.
 template <int NT, int NB>
 __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     __shared__ unsigned s_last;
@@ -498,55 +538,44 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     const int b1 = min(p.nblocks, b0 + p.group);
     const int ngroups = (p.nblocks + p.group - 1) / p.group;
 
-    // The barrier orders every wave's stores before thread 0's agent-scope
-    // release fence; the ticket itself can then be a relaxed atomic.
+    // Every thread's partial stores complete before the barrier, and the
+    // barrier before thread 0's ticket.
+    publish_wait();
     __syncthreads();
     if (threadIdx.x == 0) {
-        release_agent();
         const unsigned prev = __hip_atomic_fetch_add(&p.counters[grp], 1u, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == (unsigned)(b1 - b0 - 1)) ? 1u : 0u;
-        if (s_last) acquire_agent();
     }
     __syncthreads();
     if (!s_last) return;
 
-    if (W <= NT) {   // one entry per thread
-        double v[1];
-        ordered_sums<1>(p.partials + (int64_t)b0 * W, b1 - b0, W, threadIdx.x, NT, W, v);
-        if ((int)threadIdx.x < W) p.gpart[(int64_t)grp * W + threadIdx.x] = v[0];
-    } else {
-        for (int k0 = threadIdx.x; k0 < W; k0 += 4 * NT) {
-            double v[4];
-            ordered_sums<4>(p.partials + (int64_t)b0 * W, b1 - b0, W, k0, NT, W, v);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (k0 + q * NT < W) p.gpart[(int64_t)grp * W + k0 + q * NT] = v[q];
-        }
-    }
-    if (threadIdx.x == 0)
-        __hip_atomic_store(&p.counters[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
-    __syncthreads();
+    const double* fin = p.partials;   // what the final sums add: block or group partials
+    int nfin = p.nblocks;
     if (ngroups > 1) {
+        double* gp = p.gpart + (int64_t)grp * W;
+        block_sums<NT>(p.partials + (int64_t)b0 * W, b1 - b0, W, W,
+                       [&](int i, double v) { publish(gp + i, v); });
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&p.counters[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // second level: the last group to finish adds the group sums
+        publish_wait();
+        __syncthreads();
         if (threadIdx.x == 0) {
-            release_agent();
             const unsigned prev = __hip_atomic_fetch_add(&p.counters[ngroups], 1u, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
             s_last = (prev == (unsigned)(ngroups - 1)) ? 1u : 0u;
-            if (s_last) acquire_agent();
         }
         __syncthreads();
         if (!s_last) return;
+        fin = p.gpart;
+        nfin = ngroups;
     }
 
-    // Final sums in group order, plus each slot's Gaussian prior N(m, prec^-1 I).
-    // The nb x (1 + K) entries are spread over the block, one per thread or,
-    // when there are more, four per thread and round (one memory latency per
-    // round); each slot's squared distance to
-    // its prior mean is summed per thread, then per wave (butterfly), then
-    // over the waves in order.
+    // Final sums in block or group order, plus each slot's Gaussian prior
+    // N(m, prec^-1 I).  The nb x (1 + K) entries are spread over the block
+    // (block_sums); each slot's squared distance to its prior mean is summed
+    // per thread, then per wave (butterfly), then over the waves in order.
     __shared__ double s_flik[NB];
     __shared__ double s_pw[NT / 64][NB];
     const int nbk = p.nb * K1;
@@ -567,19 +596,7 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
         for (int bb = 0; bb < NB; ++bb)
             if (bb == b) pf[bb] += d * d;
     };
-    if (nbk <= NT) {   // one entry per thread
-        double sv[1];
-        ordered_sums<1>(p.gpart, ngroups, W, threadIdx.x, NT, nbk, sv);
-        if ((int)threadIdx.x < nbk) final_entry(threadIdx.x, sv[0]);
-    } else {
-        for (int i0 = threadIdx.x; i0 < nbk; i0 += 4 * NT) {
-            double sv[4];
-            ordered_sums<4>(p.gpart, ngroups, W, i0, NT, nbk, sv);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (i0 + q * NT < nbk) final_entry(i0 + q * NT, sv[q]);
-        }
-    }
+    block_sums<NT>(fin, nfin, W, nbk, final_entry);
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -602,7 +619,8 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     __syncthreads();
     if (p.chain) chain_step<NT>(*p.chain, p.out, p.K);
     if (threadIdx.x == 0)
-        __hip_atomic_store(&p.counters[ngroups], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&p.counters[ngroups > 1 ? ngroups : 0], 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------ wave tiles
@@ -1009,13 +1027,13 @@ __device__ __forceinline__ void block_merge(const FgParams& p, const int blk, co
                 sacc = gsh[0][b][k];
             }
             if constexpr (DT == DT_FP8) sacc *= (double)p.scale[k];
-            part[b * K1 + 1 + k] = sacc;
+            publish(&part[b * K1 + 1 + k], sacc);
         }
         if (threadIdx.x == 0) {
             double sacc = 0.0;
 #pragma unroll
             for (int w = 0; w < WPB; ++w) sacc += fsh[w][b];
-            part[b * K1] = sacc;
+            publish(&part[b * K1], sacc);
         }
     }
     merge_partials<WPB * 64, NB>(p, blk);

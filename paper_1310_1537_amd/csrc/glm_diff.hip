@@ -27,6 +27,7 @@
 
 #include "runtime.hpp"
 #include "elem.hpp"
+#include "publish.hpp"
 #include "tr_math.hpp"
 
 namespace glmrt {
@@ -143,9 +144,8 @@ __device__ __forceinline__ void load4(const void* col, int64_t n0, float s, doub
     }
 }
 
-// One block per compute unit (NT lanes): every block makes one agent-scope
-// release fence before its ticket, and those fences (L2 write-back) are what
-// a grid of many small blocks would pay for.
+// One block per compute unit (NT lanes): every block publishes a partial and
+// takes a ticket, costs that a grid of many small blocks would multiply.
 //
 // Rows are taken in groups of four (one vector load of the column, two of
 // u, one of y), two groups per loop trip with all loads issued first; the
@@ -223,18 +223,18 @@ __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
     if (threadIdx.x < nd) {
         double v = 0.0;
         for (int w = 0; w < NT / 64; ++w) v += s_w[w][threadIdx.x];
-        p.partials[(int64_t)blockIdx.x * nd + threadIdx.x] = v;
+        glmk::publish(&p.partials[(int64_t)blockIdx.x * nd + threadIdx.x], v);
     }
 
     // last block: partials in block order, plus the prior at beta + delta e_k
+    // (published partials: stores complete before the barrier and the ticket)
     __shared__ unsigned s_last;
+    glmk::publish_wait();
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned prev =
             __hip_atomic_fetch_add(p.ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = prev == gridDim.x - 1 ? 1u : 0u;
-        if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     if (!s_last) return;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
             if (j < nd) {
 #pragma unroll 8
                 for (int blk = g; blk < (int)gridDim.x; blk += 16)
-                    v += p.partials[(int64_t)blk * nd + j];
+                    v += glmk::fetch_published(&p.partials[(int64_t)blk * nd + j]);
             }
             if (j < DMAX) s_m[g][j] = v;
         }

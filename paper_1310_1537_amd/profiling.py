@@ -28,10 +28,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 _CSRC = os.path.join(ROOT, "paper_1310_1537_amd", "csrc")
 # the sources each measured kernel is built from
 KERNEL_SOURCES = {
-    "plain": ("tr_math.hpp", "rng.hpp", "fg_kernel.hpp", "glm_plain.hip"),
-    "batched": ("tr_math.hpp", "rng.hpp", "fg_kernel.hpp", "fg_batched.hpp", "glm_batched.hip"),
-    "diff": ("tr_math.hpp", "elem.hpp", "glm_diff.hip"),
-    "mx": ("tr_math.hpp", "rng.hpp", "fg_kernel.hpp", "fg_mfma.hpp", "glm_multi_mx.hip"),
+    "plain": ("tr_math.hpp", "rng.hpp", "publish.hpp", "fg_kernel.hpp", "glm_plain.hip"),
+    "batched": ("tr_math.hpp", "rng.hpp", "publish.hpp", "fg_kernel.hpp", "fg_batched.hpp",
+                "glm_batched.hip"),
+    "diff": ("tr_math.hpp", "elem.hpp", "publish.hpp", "glm_diff.hip"),
+    "mx": ("tr_math.hpp", "rng.hpp", "publish.hpp", "fg_kernel.hpp", "fg_mfma.hpp",
+           "glm_multi_mx.hip"),
 }
 
 
