@@ -1287,7 +1287,7 @@ def bench_multi(args):
     2 GB of X for every storage type and row width of the serving workload:
     microseconds per launch and per vector at 1, 2, 4 and 8 vectors; for BF16
     rows of 65 columns and more at 4 and 8 vectors, the matrix-core form beside
-    the VALU one (GLM_MFMA=0).  X ~ N(0, 1) drawn on the device (BF16 codes
+    the VALU one (context option GLM_OPT_MATRIX_CORES = 0).  X ~ N(0, 1) drawn on the device (BF16 codes
     by the library's encoder), y ~ Bernoulli(1/2), beta ~ N(0, 0.01^2 I).
     The headline value is vector evaluations per second of the BF16 K = 512
     pass of four vectors on the matrix cores."""
@@ -1338,23 +1338,21 @@ def bench_multi(args):
                 ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y, dtype=code))
                 nbytes = N * (K * es + 1)
                 for nb in (1, 2, 4, 8):
-                    forms = [("vector ALU", "0"), ("matrix cores", "1")] \
+                    forms = [("vector ALU", 0), ("matrix cores", 1)] \
                         if dt == "bf16" and K >= 65 and nb >= 4 else [("vector ALU", None)]
-                    for form, env in forms:
-                        if env is not None:
-                            os.environ["GLM_MFMA"] = env
+                    for form, mx in forms:
+                        glm.glm_set_option(ctx, glm.GLM_OPT_MATRIX_CORES, 1 if mx is None else mx)
                         us = timed(ds, K, nb)
                         rows.append({"K": K, "storage": dt, "nb": nb, "form": form, "N": N,
                                      "us_per_launch": us, "us_per_vector": us / nb,
                                      "GBps_x_once": nbytes / us / 1e3})
-                        if dt == "bf16" and K == 512 and nb == 4 and env == "1":
+                        if dt == "bf16" and K == 512 and nb == 4 and mx == 1:
                             keep = rows[-1]
-                os.environ.pop("GLM_MFMA", None)
+                glm.glm_set_option(ctx, glm.GLM_OPT_MATRIX_CORES, 1)
                 glm.glm_dataset_unregister(ctx, ds)
                 del X, y
                 torch.cuda.empty_cache()
     finally:
-        os.environ.pop("GLM_MFMA", None)
         glm.glm_destroy(ctx)
     wall = time.perf_counter() - t0
     for r in rows:

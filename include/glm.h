@@ -135,8 +135,34 @@ glm_status glm_create(int device, glm_ctx** out);
 
 /* Frees everything the context allocated, after synchronising its device.
  * Data sets and group sets still registered are released (not the caller's
- * buffers).  NULL is accepted. */
+ * buffers).  NULL is accepted.  Everything is freed even when a HIP call
+ * fails; the first failure is then returned as GLM_EHIP (its message in
+ * glm_last_error) after the context is gone. */
 glm_status glm_destroy(glm_ctx* ctx);
+
+/* Context options: launch-shape choices that change row order or kernel
+ * form, so that two contexts with the same options give the same bits.
+ *   GLM_OPT_BLOCKS_PER_CU  persistent-grid blocks per compute unit, 1..8
+ *                          (default 1); read when a data set is registered
+ *                          (it fixes that set's plan and merge shape).
+ *   GLM_OPT_INTERLEAVE     1 (default): the waves sweep row batches grid-
+ *                          strided; 0: one contiguous range per wave.  Read
+ *                          at registration.
+ *   GLM_OPT_MATRIX_CORES   1 (default): BF16 passes of 4 or more vectors with
+ *                          rows of at most 512 columns run the linear
+ *                          predictors on the matrix cores; 0: on the VALU.
+ *                          Read when a several-beta kernel is chosen (each
+ *                          glm_logpost_grad_multi call; a server's data set
+ *                          when it is added).
+ * Errors: GLM_EINVAL (NULL ctx or value pointer, unknown option, value out of
+ * range). */
+enum {
+    GLM_OPT_BLOCKS_PER_CU = 1,
+    GLM_OPT_INTERLEAVE = 2,
+    GLM_OPT_MATRIX_CORES = 3
+};
+glm_status glm_set_option(glm_ctx* ctx, int32_t option, int64_t value);
+glm_status glm_get_option(glm_ctx* ctx, int32_t option, int64_t* value);
 
 /* Message for the last error raised on the calling thread ("" if none). */
 const char* glm_last_error(void);

@@ -345,30 +345,70 @@ __device__ __forceinline__ void ordered_sums(const double* a, int n, int64_t str
 
 // The sums over n published partials (stride doubles apart) of the E entries
 // idx < E, for all NT threads of a block; emit(idx, sum) is called once per
-// entry by one thread (entry idx < NT by thread idx).  When the entries
-// leave threads idle and n needs more than one round of loads, the partials
-// are cut into C contiguous chunks, one thread per (chunk, entry) adds its
-// chunk in order and the chunk sums are added in chunk order through LDS:
-// fewer dependent load rounds, and an order fixed by (n, E, NT), so repeated
-// calls agree bitwise.  Otherwise one entry per thread, or four per thread
-// and round when E > NT.
+// entry by one thread (entry idx < NT by thread idx).  Loads of partials that
+// other blocks wrote cost per cache line a wave touches more than per load,
+// so the forms below keep each wave's lines few:
+//   - more than 16 partials but a small total (n x stride <= kStageDoubles):
+//     every double of the n partials is copied into LDS with contiguous
+//     loads spread over the whole block, then thread (c, e) adds entry e
+//     over its contiguous chunk c of the partials and the chunk sums are
+//     added in chunk order (for 16 or fewer, one round of loads by the
+//     threads of the entries is quicker);
+//   - otherwise, when the entries leave threads idle and n needs more than
+//     one round of loads, the same chunks are loaded directly;
+//   - otherwise one entry per thread, or four per thread and round when
+//     E > NT.
+// The order of every sum is fixed by (n, stride, E, NT), so repeated calls
+// agree bitwise.
+constexpr int kStageDoubles = 2048;
+
 template <int NT, typename Emit>
 __device__ __forceinline__ void block_sums(const double* a, int n, int64_t stride, int E,
-                                           Emit&& emit) {
+                                           double* s_stage, double* s_part, Emit&& emit) {
+    if (n > 16 && E <= NT && (int64_t)n * stride <= kStageDoubles) {
+        const int tot = n * (int)stride;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)a, 0, tot * 8, kRsrcWord3);
+        constexpr int L = kStageDoubles / NT;
+        double v[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(
+                rs, (uint32_t)(threadIdx.x + j * NT) * 8u, 0, kLoadPublished);
+            v[j] = __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            if ((int)threadIdx.x + j * NT < tot) s_stage[threadIdx.x + j * NT] = v[j];
+        __syncthreads();
+        const int C = min(NT / E, n);
+        const int t = threadIdx.x, c = t / E, e = t - c * E;
+        if (c < C) {
+            double sum = 0.0;
+            for (int b = c * n / C; b < (c + 1) * n / C; ++b) sum += s_stage[b * (int)stride + e];
+            s_part[t] = sum;
+        }
+        __syncthreads();
+        if (t < E) {
+            double sum = 0.0;
+            for (int cc = 0; cc < C; ++cc) sum += s_part[cc * E + t];
+            emit(t, sum);
+        }
+        return;
+    }
     const int C = min(NT / max(E, 1), (n + 15) / 16);
     if (C >= 2) {
-        __shared__ double s_chunk[NT];
         const int t = threadIdx.x, c = t / E, e = t - c * E;
         if (c < C) {
             const int t0 = c * n / C, t1 = (c + 1) * n / C;
             double v[1];
             ordered_sums<1>(a + (int64_t)t0 * stride, t1 - t0, stride, e, 0, E, v);
-            s_chunk[t] = v[0];
+            s_part[t] = v[0];
         }
         __syncthreads();
         if (t < E) {
             double sum = 0.0;
-            for (int cc = 0; cc < C; ++cc) sum += s_chunk[cc * E + t];
+            for (int cc = 0; cc < C; ++cc) sum += s_part[cc * E + t];
             emit(t, sum);
         }
     } else if (E <= NT) {
@@ -531,6 +571,8 @@ __device__ __forceinline__ void chain_step(const ChainParams& c, const double* f
 template <int NT, int NB>
 __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     __shared__ unsigned s_last;
+    __shared__ double s_stage[kStageDoubles];   // block_sums' staging and chunk sums
+    __shared__ double s_part[NT];
     const int K1 = p.K + 1;
     const int W = NB * K1;           // doubles per partial
     const int grp = blk / p.group;
@@ -554,7 +596,7 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     int nfin = p.nblocks;
     if (ngroups > 1) {
         double* gp = p.gpart + (int64_t)grp * W;
-        block_sums<NT>(p.partials + (int64_t)b0 * W, b1 - b0, W, W,
+        block_sums<NT>(p.partials + (int64_t)b0 * W, b1 - b0, W, W, s_stage, s_part,
                        [&](int i, double v) { publish(gp + i, v); });
         if (threadIdx.x == 0)
             __hip_atomic_store(&p.counters[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -582,6 +624,14 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
     double pf[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) pf[b] = 0.0;
+    // beta_k - m_k of entry idx; entry threadIdx.x (the one this thread
+    // finishes unless nb (1 + K) > NT) is loaded before the sums' loads
+    auto prior_diff = [&](int idx) {
+        const int b = idx / K1, k = idx - b * K1;
+        const int64_t bk = (int64_t)b * p.K + k - 1;
+        return k == 0 ? 0.0 : p.beta[bk] - (p.mean ? p.mean[bk] : 0.0);
+    };
+    const double d_own = (int)threadIdx.x < nbk ? prior_diff(threadIdx.x) : 0.0;
     auto final_entry = [&](int idx, double sum) {
         const int b = idx / K1, k = idx - b * K1;
         if (k == 0) {
@@ -589,14 +639,13 @@ __device__ __forceinline__ void merge_partials(const FgParams& p, int blk) {
             return;
         }
         const double prec = p.precs ? p.precs[b] : p.prec;
-        const int64_t bk = (int64_t)b * p.K + k - 1;
-        const double d = p.beta[bk] - (p.mean ? p.mean[bk] : 0.0);
+        const double d = idx == (int)threadIdx.x ? d_own : prior_diff(idx);
         p.out[(int64_t)b * K1 + k] = sum - prec * d;
 #pragma unroll
         for (int bb = 0; bb < NB; ++bb)
             if (bb == b) pf[bb] += d * d;
     };
-    block_sums<NT>(fin, nfin, W, nbk, final_entry);
+    block_sums<NT>(fin, nfin, W, nbk, s_stage, s_part, final_entry);
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll

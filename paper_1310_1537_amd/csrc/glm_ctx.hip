@@ -165,19 +165,60 @@ glm_status glm_create(int device, glm_ctx** out) {
 glm_status glm_destroy(glm_ctx* ctx) {
     clear_error();
     if (!ctx) return GLM_OK;
-    hipSetDevice(ctx->device);
-    hipDeviceSynchronize();
+    // every release is attempted; the first failure is reported
+    hipError_t first = hipSuccess;
+    const char* what = nullptr;
+    auto note = [&](hipError_t e, const char* call) {
+        if (e != hipSuccess && first == hipSuccess) {
+            first = e;
+            what = call;
+        }
+    };
+    note(hipSetDevice(ctx->device), "hipSetDevice");
+    note(hipDeviceSynchronize(), "hipDeviceSynchronize");
     for (auto& kv : ctx->scratch)
-        if (kv.second.base) hipFree(kv.second.base);
+        if (kv.second.base) note(hipFree(kv.second.base), "hipFree(scratch)");
     for (auto& kv : ctx->sampler)
-        if (kv.second.buf) hipFree(kv.second.buf);
+        if (kv.second.buf) note(hipFree(kv.second.buf), "hipFree(sampler)");
     for (auto& kv : ctx->hess)
-        if (kv.second.buf) hipFree(kv.second.buf);
-    if (ctx->h_stage) hipHostFree(ctx->h_stage);
-    if (ctx->d_stage) hipFree(ctx->d_stage);
-    if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+        if (kv.second.buf) note(hipFree(kv.second.buf), "hipFree(hessian)");
+    if (ctx->h_stage) note(hipHostFree(ctx->h_stage), "hipHostFree(stage)");
+    if (ctx->d_stage) note(hipFree(ctx->d_stage), "hipFree(stage)");
+    if (ctx->own_stream) note(hipStreamDestroy(ctx->own_stream), "hipStreamDestroy");
     delete ctx;
+    if (first != hipSuccess)
+        GLM_FAIL(GLM_EHIP, "glm_destroy: %s: %s", what, hipGetErrorString(first));
     return GLM_OK;
+}
+
+glm_status glm_set_option(glm_ctx* ctx, int32_t option, int64_t value) {
+    clear_error();
+    if (!ctx) GLM_FAIL(GLM_EINVAL, "glm_set_option: NULL context");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    switch (option) {
+    case GLM_OPT_BLOCKS_PER_CU:
+        if (value < 1 || value > 8) GLM_FAIL(GLM_EINVAL, "glm_set_option: blocks per CU %lld outside [1, 8]", (long long)value);
+        ctx->blocks_per_cu = (int)value;
+        return GLM_OK;
+    case GLM_OPT_INTERLEAVE:
+    case GLM_OPT_MATRIX_CORES:
+        if (value != 0 && value != 1) GLM_FAIL(GLM_EINVAL, "glm_set_option: option %d takes 0 or 1, not %lld", option, (long long)value);
+        (option == GLM_OPT_INTERLEAVE ? ctx->interleave : ctx->matrix_cores) = value != 0;
+        return GLM_OK;
+    }
+    GLM_FAIL(GLM_EINVAL, "glm_set_option: unknown option %d", option);
+}
+
+glm_status glm_get_option(glm_ctx* ctx, int32_t option, int64_t* value) {
+    clear_error();
+    if (!ctx || !value) GLM_FAIL(GLM_EINVAL, "glm_get_option: NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    switch (option) {
+    case GLM_OPT_BLOCKS_PER_CU: *value = ctx->blocks_per_cu; return GLM_OK;
+    case GLM_OPT_INTERLEAVE: *value = ctx->interleave ? 1 : 0; return GLM_OK;
+    case GLM_OPT_MATRIX_CORES: *value = ctx->matrix_cores ? 1 : 0; return GLM_OK;
+    }
+    GLM_FAIL(GLM_EINVAL, "glm_get_option: unknown option %d", option);
 }
 
 glm_status glm_dataset_register(glm_ctx* ctx, const glm_dataset_desc* d, glm_dataset_id* out) {

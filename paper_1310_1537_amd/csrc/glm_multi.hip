@@ -2,26 +2,14 @@
 // data set per launch, and the fleet form that runs the passes of several
 // data sets of one geometry in one launch), and the public entry point
 // glm_logpost_grad_multi.
-#include <cstdlib>
-
 #include "fg_kernel.hpp"
 #include "multi_inst.hpp"
 #include "runtime.hpp"
 
 namespace glmrt {
-namespace {
 
-// GLM_MFMA=0 keeps BF16 passes on the VALU kernels (for comparisons); read
-// at every choice of instance, so a process can time both forms.
-bool mx_enabled() {
-    const char* e = std::getenv("GLM_MFMA");
-    return !e || std::atoi(e) != 0;
-}
-
-}  // namespace
-
-MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max) {
-    if (dtype == GLM_BF16 && cpl == 1 && nb_max >= 4 && mx_enabled()) {
+MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max, bool mx) {
+    if (dtype == GLM_BF16 && cpl == 1 && nb_max >= 4 && mx) {
         const MultiInst m = mx_instance(lpr);
         if (m.fn) return m;
     }
@@ -66,7 +54,7 @@ glm_status glm_logpost_grad_multi(glm_ctx* ctx, glm_dataset_id id, const double*
     if (st != GLM_OK) return st;
     const Dataset& ds = it->second;
     const int K = ds.d.K;
-    MultiInst mi = multi_instance(ds.d.dtype, ds.plan.lpr, ds.plan.cpl, nb);
+    MultiInst mi = multi_instance(ds.d.dtype, ds.plan.lpr, ds.plan.cpl, nb, ctx->matrix_cores);
     int NB = mi.fn ? mi.NB : 1;
     const void* fn = mi.fn ? mi.fn : ds.plan.fn;
     Plan plan = ds.plan;

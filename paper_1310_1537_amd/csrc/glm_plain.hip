@@ -93,15 +93,15 @@ glm_status make_plan(glm_ctx* ctx, const glm_dataset_desc& d, Plan* plan) {
     // Persistent grid: every wave streams one contiguous range of row batches.
     const int64_t wave_rows = (int64_t)in.R * (64 / p.lpr);
     const int64_t nbatch = (d.N + wave_rows - 1) / wave_rows;
-    int bpc = 1;
-    if (const char* e = std::getenv("GLM_BLOCKS_PER_CU")) bpc = std::max(1, std::atoi(e));
-    const int64_t target = (int64_t)ctx->num_cu * bpc;
+    const int64_t target = (int64_t)ctx->num_cu * ctx->blocks_per_cu;
     const int64_t need = (nbatch + p.wpb - 1) / p.wpb;
     p.nblocks = (int)std::max<int64_t>(1, std::min(need, target));
-    p.interleave = 1;
-    if (const char* e = std::getenv("GLM_INTERLEAVE")) p.interleave = std::atoi(e) != 0;
-    // one merge level for small grids, two (groups of about sqrt(nblocks)) above
-    p.group = p.nblocks <= 64 ? p.nblocks : std::max(1, (int)std::ceil(std::sqrt((double)p.nblocks)));
+    p.interleave = ctx->interleave ? 1 : 0;
+    // One merge level for small grids (64 blocks or fewer, or block partials
+    // of one vector that fit the merge's LDS staging), two (groups of about
+    // sqrt(nblocks)) above.
+    const bool one_level = p.nblocks <= 64 || (int64_t)p.nblocks * (d.K + 1) <= glmk::kStageDoubles;
+    p.group = one_level ? p.nblocks : std::max(1, (int)std::ceil(std::sqrt((double)p.nblocks)));
     *plan = p;
     return GLM_OK;
 }

@@ -773,7 +773,8 @@ glm_status glm_server_add_dataset(glm_server* s, const glm_dataset_desc* d, int3
     if (!ds.on_device) probe.X = nullptr;
     st = make_plan(s->ctx, probe, &ds.plan);
     if (st != GLM_OK) return st;
-    ds.mi = multi_instance(d->dtype, ds.plan.lpr, ds.plan.cpl, s->cfg.max_beta_per_pass);
+    ds.mi = multi_instance(d->dtype, ds.plan.lpr, ds.plan.cpl, s->cfg.max_beta_per_pass,
+                           s->ctx->matrix_cores);
     if (ds.on_device) {
         ds.dev = *d;
         ds.state = DS_RESIDENT;

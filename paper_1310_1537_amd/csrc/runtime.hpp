@@ -110,6 +110,10 @@ struct glm_ctx {
     int device = 0;
     int num_cu = 256;
     std::string arch;
+    // options (glm_set_option)
+    int blocks_per_cu = 1;
+    bool interleave = true;
+    bool matrix_cores = true;
     std::mutex mu;
     int64_t next_id = 1;
     std::unordered_map<int64_t, glmrt::Dataset> datasets;
@@ -151,7 +155,9 @@ struct MultiInst {
     const void* fleet = nullptr;   // the same geometry over several data sets per launch
     int wpb = 4;                   // waves per block of both forms
 };
-MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max);
+// The several-beta instance for nb_max vectors per pass; BF16 passes of four
+// or more take the matrix-core form when mx is set and one exists.
+MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max, bool mx);
 
 // The matrix-core instance for BF16 rows of lpr lanes (4 vectors per pass),
 // fn == nullptr where none is built.

@@ -26,6 +26,7 @@ GLM_EBUDGET, GLM_ECANCELLED, GLM_EAGAIN, GLM_ENOMEM = -5, -6, -7, -8
 GLM_F64, GLM_F32, GLM_BF16, GLM_FP8_E4M3 = 0, 1, 2, 3
 GLM_LOGISTIC, GLM_POISSON = 0, 1
 GLM_K_MAX = 4096
+GLM_OPT_BLOCKS_PER_CU, GLM_OPT_INTERLEAVE, GLM_OPT_MATRIX_CORES = 1, 2, 3
 
 STATUS_NAMES = {0: "GLM_OK", 1: "GLM_PENDING", -1: "GLM_EINVAL", -2: "GLM_EDTYPE",
                 -3: "GLM_EHIP", -4: "GLM_ENOTFOUND", -5: "GLM_EBUDGET",
@@ -92,6 +93,8 @@ _PP = ctypes.POINTER(ctypes.c_void_p)
 _SIGS = {
     "glm_create": [ctypes.c_int, _PP],
     "glm_destroy": [_P],
+    "glm_set_option": [_P, _I32, _I64],
+    "glm_get_option": [_P, _I32, ctypes.POINTER(_I64)],
     "glm_dataset_register": [_P, ctypes.POINTER(glm_dataset_desc), ctypes.POINTER(_I64)],
     "glm_dataset_unregister": [_P, _I64],
     "glm_logpost_grad": [_P, _I64, _P, ctypes.POINTER(glm_prior), _P, _P],
@@ -192,6 +195,16 @@ def glm_create(device: int = 0) -> int:
 
 def glm_destroy(ctx: int) -> None:
     _check(_lib.glm_destroy(ctx))
+
+
+def glm_set_option(ctx: int, option: int, value: int) -> None:
+    _check(_lib.glm_set_option(ctx, option, value))
+
+
+def glm_get_option(ctx: int, option: int) -> int:
+    out = _I64()
+    _check(_lib.glm_get_option(ctx, option, ctypes.byref(out)))
+    return out.value
 
 
 # ---------------------------------------------------------------- data sets

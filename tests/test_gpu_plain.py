@@ -255,3 +255,32 @@ def test_aligned_rows_helper_and_rejection(ctx):
     assert Xa.stride(0) == 12
     f, g = eval_gpu(ctx, Xa, yd, beta, 0.01)
     check_against_oracle(f, g, X.astype(np.float64), y, beta, 0.01)
+
+
+@pytest.mark.parametrize("bpc,interleave", [(2, 1), (1, 0), (3, 0)])
+@pytest.mark.parametrize("N,K", [(40_003, 32), (200_001, 256), (7_001, 20)])
+def test_context_launch_options(bpc, interleave, N, K):
+    """GLM_OPT_BLOCKS_PER_CU and GLM_OPT_INTERLEAVE change the grid and the
+    row order of data sets registered afterwards: every shape stays within
+    the oracle bound and repeats bitwise under its options."""
+    c = Ctx()
+    try:
+        assert glm.glm_get_option(c.h, glm.GLM_OPT_BLOCKS_PER_CU) == 1
+        assert glm.glm_get_option(c.h, glm.GLM_OPT_INTERLEAVE) == 1
+        glm.glm_set_option(c.h, glm.GLM_OPT_BLOCKS_PER_CU, bpc)
+        glm.glm_set_option(c.h, glm.GLM_OPT_INTERLEAVE, interleave)
+        assert glm.glm_get_option(c.h, glm.GLM_OPT_BLOCKS_PER_CU) == bpc
+        X, y, beta = sweeps.plain_f32_case(N, K)
+        Xd, yd = to_dev(X), to_dev(y)
+        sweep_point(c.h, Xd, yd, X.astype(np.float64), y, beta, 0.01)
+        ds = glm.glm_dataset_register(c.h, glm.make_desc(Xd, yd))
+        f1, g1 = eval_gpu(c.h, Xd, yd, beta, 0.01, ds=ds)
+        f2, g2 = eval_gpu(c.h, Xd, yd, beta, 0.01, ds=ds)
+        assert f1 == f2 and np.array_equal(g1, g2)
+        glm.glm_dataset_unregister(c.h, ds)
+        for opt, bad in ((glm.GLM_OPT_BLOCKS_PER_CU, 0), (glm.GLM_OPT_BLOCKS_PER_CU, 9),
+                         (glm.GLM_OPT_INTERLEAVE, 2), (glm.GLM_OPT_MATRIX_CORES, -1), (99, 1)):
+            with pytest.raises(glm.GlmError):
+                glm.glm_set_option(c.h, opt, bad)
+    finally:
+        c.close()

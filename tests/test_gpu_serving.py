@@ -476,28 +476,32 @@ def test_multi_bf16_matrix_core(ctx, K, nb):
 
 
 @pytest.mark.parametrize("K", [100, 512])
-def test_multi_bf16_vector_alu_form(ctx, K, monkeypatch):
-    """GLM_MFMA=0 keeps BF16 passes of four vectors on the VALU kernels; that
-    form and the matrix-core one both stay within the oracle bound."""
+def test_multi_bf16_vector_alu_form(ctx, K):
+    """The context option GLM_OPT_MATRIX_CORES = 0 keeps BF16 passes of four
+    vectors on the VALU kernels; that form and the matrix-core one both stay
+    within the oracle bound."""
     X, y, bt = _data(6_007, K, 500 + K)
     Q = oracle.quantize_bf16(X)
     Qd, yd = glm.aligned_rows(to_dev(Q)), to_dev(y)
     ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
     B = _betas(bt, 4, 501 + K)
     res = {}
-    for env in ("0", "1"):
-        monkeypatch.setenv("GLM_MFMA", env)
-        out = torch.empty((4, K + 1), dtype=torch.float64, device=DEV)
-        glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), 4, glm.make_prior(0.01), out)
-        torch.cuda.synchronize()
-        res[env] = out.cpu().numpy()
-    monkeypatch.delenv("GLM_MFMA")
+    try:
+        for mx in (0, 1):
+            glm.glm_set_option(ctx, glm.GLM_OPT_MATRIX_CORES, mx)
+            assert glm.glm_get_option(ctx, glm.GLM_OPT_MATRIX_CORES) == mx
+            out = torch.empty((4, K + 1), dtype=torch.float64, device=DEV)
+            glm.glm_logpost_grad_multi(ctx, ds, to_dev(B), 4, glm.make_prior(0.01), out)
+            torch.cuda.synchronize()
+            res[mx] = out.cpu().numpy()
+    finally:
+        glm.glm_set_option(ctx, glm.GLM_OPT_MATRIX_CORES, 1)
     glm.glm_dataset_unregister(ctx, ds)
     for env, o in res.items():
         for b in range(4):
             _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, B[b], 0.01, storage="bf16", Xo=Q,
                    okw={"dtype": "bf16"})
-    assert not np.array_equal(res["0"], res["1"])   # two different kernels ran
+    assert not np.array_equal(res[0], res[1])   # two different kernels ran
 
 
 def test_multi_bf16_matrix_core_edges(ctx):
