@@ -64,22 +64,83 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
     // The wave's items are streamed as one sequence of batches, so the next
     // batch is prefetched across item boundaries too; every item yields at
     // least one batch (an empty group one empty batch).  Queue state and
-    // batch descriptors are wave-uniform (scalar registers).
+    // batch descriptors are wave-uniform (scalar registers).  The item
+    // descriptors are copied into LDS up to kItemsLds at a time, so moving to
+    // the next item waits on LDS, not on memory: a vector-memory wait would
+    // also drain the wave's tile loads in flight, and under the streaming
+    // load a dependent memory access takes microseconds.
+    constexpr int kItemsLds = 32;
+    __shared__ BatchItem s_items[WPB][kItemsLds];
+    const int lane = threadIdx.x & 63;
     const int it0 = p.wave_items[gw];
     const int it1 = p.wave_items[gw + 1];
+    int ibase = -kItemsLds;   // first item (relative to it0) held in LDS
+    auto item = [&](int it) {
+        const int rel = it - it0;
+        if (rel < ibase || rel >= ibase + kItemsLds) {   // rare: every kItemsLds items
+            ibase = rel - rel % kItemsLds;
+            if (lane < kItemsLds) {
+                const int i = it0 + ibase + lane;
+                s_items[wave][lane] = i < it1 ? p.items[i] : BatchItem{0, 0, 0, -1};
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        const BatchItem& e = s_items[wave][rel - ibase];
+        BatchItem r;
+        r.r0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(e.r0 >> 32)) << 32) |
+               (uint32_t)__builtin_amdgcn_readfirstlane((int)e.r0);
+        r.r1 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(e.r1 >> 32)) << 32) |
+               (uint32_t)__builtin_amdgcn_readfirstlane((int)e.r1);
+        r.group = __builtin_amdgcn_readfirstlane(e.group);
+        r.tile = __builtin_amdgcn_readfirstlane(e.tile);
+        return r;
+    };
     int qit = it0;                                   // item of the next batch to load
     BatchItem qitem{0, 0, 0, -1};
-    if (qit < it1) qitem = p.items[qit];
+    if (qit < it1) qitem = item(qit);
     int64_t qr = qitem.r0;                           // its first row
+
+    // Where registers allow (CPL x VE <= 8), the coefficients and prior
+    // means of the next item are loaded when an item starts (the first at
+    // the start), so starting and ending an item waits on no memory; wider
+    // rows load them when the item starts and ends.
+    constexpr bool PF = CPL * VE <= 8;
+    constexpr int PVE = PF ? VE : 1;   // prefetch array extent (unused without)
+    double pb[CPL][PVE], pm[CPL][PVE];
+    auto prefetch = [&](int g) {
+        if constexpr (PF) {
+            // buffer loads: columns past K, and a missing mean, read as zeros
+            // without a branch, so the loads write the registers directly
+            const double* mn =
+                p.mean ? (p.mean_per_group ? p.mean + (int64_t)g * K : p.mean) : nullptr;
+            const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(p.betas + (int64_t)g * K), 0, K * 8, kRsrcWord3);
+            const __amdgpu_buffer_rsrc_t rm = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(mn ? mn : p.betas), 0, mn ? K * 8 : 0, kRsrcWord3);
+#pragma unroll
+            for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                for (int e = 0; e < VE; ++e) {
+                    const uint32_t off = (uint32_t)wt.col(i, e) * 8u;
+                    const u32x2 wb = __builtin_amdgcn_raw_buffer_load_b64(rb, off, 0, 0);
+                    const u32x2 wm = __builtin_amdgcn_raw_buffer_load_b64(rm, off, 0, 0);
+                    pb[i][e] = __longlong_as_double((long long)(((unsigned long long)wb[1] << 32) | wb[0]));
+                    pm[i][e] = __longlong_as_double((long long)(((unsigned long long)wm[1] << 32) | wm[0]));
+                }
+        }
+    };
 
     struct Meta {
         int it;          // item index, it1 = none
+        int group, tile; // its group and partial slot (-1: whole group)
         int64_t row0, r1;
         bool first, last;
     };
     auto next = [&]() {
         Meta m;
         m.it = qit;
+        m.group = qitem.group;
+        m.tile = qitem.tile;
         m.row0 = qr;
         m.r1 = qit < it1 ? qitem.r1 : 0;
         m.first = qit < it1 && qr == qitem.r0;
@@ -90,7 +151,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
             } else {
                 ++qit;
                 if (qit < it1) {
-                    qitem = p.items[qit];
+                    qitem = item(qit);
                     qr = qitem.r0;
                 }
             }
@@ -98,21 +159,44 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
         return m;
     };
 
-    BatchItem citem{0, 0, 0, -1};   // item being computed
+    double dp[CPL][PVE];   // beta - prior mean per column of the item being computed (PF)
+    int cgroup = 0, ctile = -1;
     auto compute = [&](Tile& t, const Meta& m) {
         if (m.first) {
-            citem = p.items[m.it];
-            wt.set_beta(0, p.betas + (int64_t)citem.group * K, p.scale);
+            cgroup = m.group;
+            ctile = m.tile;
+            if constexpr (PF) {
+#pragma unroll
+                for (int i = 0; i < CPL; ++i)
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) {
+                        dp[i][e] = pb[i][e] - pm[i][e];
+                        if constexpr (DT == DT_FP8)
+                            wt.bd[0][i][e] = pb[i][e] * (double)p.scale[wt.col(i, e)];
+                        else
+                            wt.bd[0][i][e] = pb[i][e];
+                        // the prefetch below may reuse the registers of pb
+                        // and pm only once these are computed
+                        asm volatile("" : "+v"(dp[i][e]), "+v"(wt.bd[0][i][e]));
+                    }
+                asm volatile("" ::: "memory");
+                // unconditional (group 0 past the last item), so that the
+                // loads write the prefetch registers directly and nothing
+                // waits on them before the next item starts
+                prefetch(m.it + 1 < it1 ? item(m.it + 1).group : 0);
+            } else {
+                wt.set_beta(0, p.betas + (int64_t)cgroup * K, p.scale);
+            }
             wt.zero_acc();
         }
         wt.compute(t, (uint32_t)max((int64_t)0, min((int64_t)BATCH, m.r1 - m.row0)), rbuf[wave]);
         if (!m.last) return;
         // item done: whole group -> its result; tile of a split group -> its partial
         wt.wave_totals();
-        const int g = citem.group;
+        const int g = cgroup;
         const double* beta = p.betas + (int64_t)g * K;
         const double* mn = p.mean ? (p.mean_per_group ? p.mean + (int64_t)g * K : p.mean) : nullptr;
-        double* dst = citem.tile < 0 ? nullptr : p.partials + (int64_t)citem.tile * K1;
+        double* dst = ctile < 0 ? nullptr : p.partials + (int64_t)ctile * K1;
         double* o = p.out + (int64_t)g * K1;
         double pf = 0.0;
         if (wt.seg == 0) {
@@ -127,7 +211,9 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
                         if (dst) {
                             publish(dst + 1 + k, v);
                         } else {
-                            const double d = beta[k] - (mn ? mn[k] : 0.0);
+                            double d;
+                            if constexpr (PF) d = dp[i][e];
+                            else d = beta[k] - (mn ? mn[k] : 0.0);
                             pf += d * d;
                             o[1 + k] = v - p.prec * d;
                         }
@@ -144,6 +230,7 @@ __global__ __launch_bounds__(WPB * 64) void fg_batched(BatchedParams p) {
     Tile ta, tb;
     Meta ma = next();
     wt.load(ta, p.X, p.y, ma.row0, ma.r1 - ma.row0);
+    if (ma.it < it1) prefetch(ma.group);
     while (true) {
         const Meta mb = next();
         wt.load(tb, p.X, p.y, mb.row0, mb.r1 - mb.row0);

@@ -287,9 +287,9 @@ glm_status autotune(glm_groupset* gs) {
             const int64_t T = (int64_t)gs->batch_rows * mult;
             st = apply_schedule(gs, T, bpc);
             if (st != GLM_OK) break;
-            for (int w = 0; w < 2 && st == GLM_OK; ++w) st = launch_batched(gs, dz, &pr, dz + nbeta, nullptr);
+            for (int w = 0; w < 3 && st == GLM_OK; ++w) st = launch_batched(gs, dz, &pr, dz + nbeta, nullptr);
             if (st != GLM_OK) break;
-            const int reps = 5;
+            const int reps = 20;   // a few microseconds separate the candidates
             GLM_HIP_CHECK(hipEventRecord(e0, nullptr));
             for (int r = 0; r < reps && st == GLM_OK; ++r) st = launch_batched(gs, dz, &pr, dz + nbeta, nullptr);
             GLM_HIP_CHECK(hipEventRecord(e1, nullptr));
