@@ -708,6 +708,11 @@ struct WaveTile {
     // summed in FP32 over the R rows of a batch, then added in FP64.
     static constexpr bool G64 = F64 || (DT == DT_F32 && NB == 1);
     using rtype = typename std::conditional<G64, double, float>::type;
+    // Keeping the values decoded for the dot products for the gradient
+    // (instead of decoding a second time) was measured slower for FP8 and
+    // BF16 rows of 512 columns at every batch height tried: the register
+    // pressure costs more than the decode, so it stays off.
+    static constexpr bool KEEP = false;
 
     struct Tile {
         u32x4 x[R][CPL];
@@ -765,15 +770,23 @@ struct WaveTile {
     __device__ __forceinline__ bool elem_ok(int i, int e) const { return col(i, e) < KC; }
 
     // Coefficient vector of slot b (K doubles); FP8 folds the column scales in.
+    // Buffer loads: columns past KC read as zeros without a branch, so every
+    // load is issued before the first wait (a branch per element made the
+    // FP8 form wait for each beta and scale in turn).
     __device__ __forceinline__ void set_beta(int b, const double* beta, const float* scale) {
+        const __amdgpu_buffer_rsrc_t rb =
+            __builtin_amdgcn_make_buffer_rsrc((void*)beta, 0, KC * 8, kRsrcWord3);
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
-                double v = 0.0;
-                if (elem_ok(i, e)) {
-                    v = beta[col(i, e)];
-                    if constexpr (DT == DT_FP8) v *= (double)scale[col(i, e)];
+                const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rb, (uint32_t)col(i, e) * 8u, 0, 0);
+                double v = __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+                if constexpr (DT == DT_FP8) {
+                    const __amdgpu_buffer_rsrc_t rs =
+                        __builtin_amdgcn_make_buffer_rsrc((void*)scale, 0, KC * 4, kRsrcWord3);
+                    v *= (double)__builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)col(i, e) * 4u, 0, 0));
                 }
                 bd[b][i][e] = v;
             }
@@ -834,6 +847,7 @@ struct WaveTile {
 #pragma unroll
                 for (int i = 0; i < CPL; ++i) t.x[j][i] &= xmask[i];
         }
+        float xk[KEEP ? R : 1][CPL][KEEP ? VE : 1];   // decoded tile (KEEP)
         double ub[NB];   // the owned row's u per slot (SPLIT_TR)
 #pragma unroll
         for (int b = 0; b < NB; ++b) ub[b] = 0.0;
@@ -872,7 +886,10 @@ struct WaveTile {
                         float xv[VE];
                         decode_chunk<DT>(raw, xv);
 #pragma unroll
-                        for (int e = 0; e < VE; ++e) sacc = fma((double)xv[e], bd[b][i][e], sacc);
+                        for (int e = 0; e < VE; ++e) {
+                            if constexpr (KEEP) xk[j][i][e] = xv[e];
+                            sacc = fma((double)xv[e], bd[b][i][e], sacc);
+                        }
                     }
                     v[j] = sacc;
                 }
@@ -955,13 +972,19 @@ struct WaveTile {
                 for (int j = 0; j < R; ++j)
 #pragma unroll
                     for (int i = 0; i < CPL; ++i) {
-                        u32x4 raw = t.x[j][i];
-                        // Decode again rather than keep the decoded tile of the
-                        // dot-product phase alive (VE floats per 4 raw registers):
-                        // the empty asm hides that raw is unchanged.
-                        if constexpr (VE > 4) asm volatile("" : "+v"(raw));
                         float xv[VE];
-                        decode_chunk<DT>(raw, xv);
+                        if constexpr (KEEP) {
+#pragma unroll
+                            for (int e = 0; e < VE; ++e) xv[e] = xk[j][i][e];
+                        } else {
+                            u32x4 raw = t.x[j][i];
+                            // Decode again rather than keep the decoded tile of
+                            // the dot-product phase alive (VE floats per 4 raw
+                            // registers): the empty asm hides that raw is
+                            // unchanged.
+                            if constexpr (VE > 4) asm volatile("" : "+v"(raw));
+                            decode_chunk<DT>(raw, xv);
+                        }
 #pragma unroll
                         for (int e = 0; e < VE; ++e) g32[i][e] = fmaf(rs[j], xv[e], g32[i][e]);
                     }
@@ -1091,8 +1114,10 @@ __device__ __forceinline__ void block_merge(const FgParams& p, const int blk, co
 // ------------------------------------------------------------ plain kernel
 
 // Block blk (of p.nblocks) of the evaluation of f and g of p.nb (<= NB)
-// coefficient vectors over all rows of one data set.
-template <int DT, int LPR, int CPL, int R, int WPB, int NB>
+// coefficient vectors over all rows of one data set.  NBUF tiles rotate in
+// the grid-strided sweep: the load of a batch is issued NBUF - 1 batches
+// before it is computed.
+template <int DT, int LPR, int CPL, int R, int WPB, int NB, int NBUF = 2>
 __device__ __forceinline__ void fg_pass(const FgParams& p, const int blk) {
     using WT = WaveTile<DT, LPR, CPL, R, NB>;
     constexpr int BATCH = WT::BATCH;
@@ -1126,20 +1151,25 @@ __device__ __forceinline__ void fg_pass(const FgParams& p, const int blk) {
     const int64_t tw = (int64_t)p.nblocks * WPB;
     const int64_t gw = (int64_t)blk * WPB + wave;
     if (p.interleave) {
-        typename WT::Tile ta, tb;
+        static_assert(NBUF >= 2, "at least double buffering");
+        typename WT::Tile tl[NBUF];
         const int64_t step = tw * BATCH;
         const int64_t rend = nbatch * BATCH;
         int64_t r = gw * BATCH;
-        wt.load(ta, p.X, p.y, r, p.N - r);
-        for (; r < rend; r += 2 * step) {
-            wt.load(tb, p.X, p.y, r + step, p.N - r - step);
-            wt.compute(ta, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r)), rbuf[wave], nact,
-                       r);
-            if (r + step >= rend) break;
-            wt.load(ta, p.X, p.y, r + 2 * step, p.N - r - 2 * step);
-            wt.compute(tb, (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - r - step)), rbuf[wave],
-                       nact, r + step);
+#pragma unroll
+        for (int j = 0; j + 1 < NBUF; ++j) wt.load(tl[j], p.X, p.y, r + j * step, p.N - r - j * step);
+        for (;; r += NBUF * step) {
+#pragma unroll
+            for (int j = 0; j < NBUF; ++j) {
+                const int64_t rj = r + j * step;
+                if (rj >= rend) goto swept;
+                const int64_t rn = rj + (NBUF - 1) * step;   // loaded into the tile just freed
+                wt.load(tl[(j + NBUF - 1) % NBUF], p.X, p.y, rn, p.N - rn);
+                wt.compute(tl[j], (uint32_t)max((int64_t)0, min((int64_t)BATCH, p.N - rj)), rbuf[wave],
+                           nact, rj);
+            }
         }
+    swept:;
     } else {
         const int64_t r0 = min(p.N, nbatch * gw / tw * BATCH);
         const int64_t r1 = min(p.N, nbatch * (gw + 1) / tw * BATCH);
@@ -1151,9 +1181,9 @@ __device__ __forceinline__ void fg_pass(const FgParams& p, const int blk) {
 
 // f and g of p.nb (<= NB) coefficient vectors over all rows of one data set
 // (the grid is p.nblocks blocks).
-template <int DT, int LPR, int CPL, int R, int WPB, int NB = 1>
+template <int DT, int LPR, int CPL, int R, int WPB, int NB = 1, int NBUF = 2>
 __global__ __launch_bounds__(WPB * 64) void fg_fused(FgParams p) {
-    fg_pass<DT, LPR, CPL, R, WPB, NB>(p, blockIdx.x);
+    fg_pass<DT, LPR, CPL, R, WPB, NB, NBUF>(p, blockIdx.x);
 }
 
 // ------------------------------------------------------------ fleet kernel

@@ -22,11 +22,17 @@ template <int DT, int LPR, int CPL>
 Inst inst() {
     // 16 row slots of 16 bytes per lane per batch (64 VGPRs per tile); FP32
     // takes 8 (its FP64 gradient products keep r in FP64, and with 16 slots
-    // the kernel no longer fits two waves per SIMD)
-    constexpr int VE = 16 / glmk::ElemSize<DT>::v;
+    // the kernel no longer fits two waves per SIMD).  Wide FP8 rows (256 to
+    // 512 columns, one chunk per lane) rotate three tiles, the load of a
+    // batch going out two batches ahead: 8M x 512 random codes take 790
+    // against about 810 us with two.  BF16 rows of 512 columns with 8 slots
+    // and three tiles were slower on random data (1,340 against 1,265 us),
+    // and FP32 and FP64 gain nothing from a third tile.
+    constexpr bool WIDE = DT == glmk::DT_FP8 && CPL == 1 && LPR >= 32;
     constexpr int RE = DT == glmk::DT_F32 ? 8 : 16;
     constexpr int R = RE / CPL > 0 ? RE / CPL : 1;
-    return Inst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, R, WPB>), R};
+    constexpr int NBUF = WIDE ? 3 : 2;
+    return Inst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, R, WPB, 1, NBUF>), R};
 }
 
 template <int DT>
