@@ -817,6 +817,39 @@ def bench_serving(args):
         print(f"[bench] one/pass rate {r}: {res_1[-1]['throughput']:.0f} req/s "
               f"p50 {res_1[-1]['latency_p50_us']:.0f} us p99 {res_1[-1]['latency_p99_us']:.0f} us",
               file=sys.stderr, flush=True)
+    # The ceiling the passes themselves set: each data set's several-beta
+    # pass of 8 vectors (the server's width) timed alone with HIP events; with
+    # requests spread evenly over the data sets (8 chains each), throughput
+    # cannot exceed 1 / (mean over data sets of the time per vector).
+    ceiling = None
+    try:
+        stream = torch.cuda.current_stream()
+        per_vec = []
+        pr = glm.make_prior(0.01)
+        for i, (X, y, dt) in enumerate(keep):
+            ds = glm.glm_dataset_register(ctx, glm.make_desc(X, y, dtype=dt))
+            K = datasets[i][0]
+            B = torch.from_numpy(np.ascontiguousarray(betas[8 * i][:8])).to(dev)
+            out = torch.empty((8, K + 1), dtype=torch.float64, device=dev)
+            for _ in range(3):
+                glm.glm_logpost_grad_multi(ctx, ds, B, 8, pr, out, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                glm.glm_logpost_grad_multi(ctx, ds, B, 8, pr, out, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            per_vec.append(e0.elapsed_time(e1) * 1e3 / 10 / 8)
+            glm.glm_dataset_unregister(ctx, ds)
+        mean_us = float(np.mean(per_vec))
+        ceiling = {"requests_per_s": 1e6 / mean_us, "mean_us_per_vector": mean_us,
+                   "frac_reached": res_b[-1]["throughput"] / (1e6 / mean_us),
+                   "note": "each data set's pass of 8 vectors (glm_logpost_grad_multi) timed "
+                           "alone; requests are spread evenly over the data sets"}
+        print(f"[bench] pass-cost ceiling {ceiling['requests_per_s']:.0f} req/s; reached "
+              f"{ceiling['frac_reached']:.2f} of it", file=sys.stderr, flush=True)
+    except Exception as e:   # recorded, not lost
+        ceiling = {"error": repr(e)}
     # binding budget: the same data sets given from pinned host memory to a
     # server whose budget holds about a third of them, so that admissions and
     # evictions churn under the open-loop load
@@ -911,6 +944,7 @@ def bench_serving(args):
                      "note": "X and y bytes of every pass (one read per pass of up to 8 "
                              "requests) over the wall time at the highest offered rate"},
         "by_rate": res_b, "one_request_per_pass": res_1, "binding_budget": budget_res,
+        "pass_cost_ceiling": ceiling,
     }
     if check is not None:
         rec["err_vs_fp64"] = check["err"]

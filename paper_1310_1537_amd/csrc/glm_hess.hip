@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "elem.hpp"
@@ -86,8 +87,16 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
     const int64_t r0 = p.N * chunk / p.nchunk;
     const int64_t r1 = p.N * (chunk + 1) / p.nchunk;
 
-    // xs[r][c]: c < kTile the i-range, c >= kTile the j-range (off-diagonal tiles)
-    __shared__ double xs[R][2 * kTile + 1];
+    // xs[r][c]: c < kTile the i-range, c >= kTile the j-range (off-diagonal
+    // tiles).  The row stride is 16 doubles past a multiple of 32 (64 banks of
+    // 4 bytes), so the two rows that one half-wave reads in the matrix loop
+    // (lanes 0-15 and 16-31, rows kk and kk + 1) fall in disjoint banks.
+    // FP32 and BF16 rows are staged as FP32 (exact; half the LDS, and each
+    // thread's 16-byte chunk goes in with one conflict-free 16-byte store),
+    // FP64 and scaled FP8 as FP64; the matrix loop converts on the read.
+    constexpr int XS = 2 * kTile + 16;
+    using LT = typename std::conditional<DT == GLM_F32 || DT == GLM_BF16, float, double>::type;
+    __shared__ LT xs[R][XS];
     __shared__ double ws[R];
 
     const int cw = diag ? CR : 2 * CR;                 // staged chunks per row
@@ -117,7 +126,8 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
         wl = p.w[min(r + (int64_t)(threadIdx.x % R), r1 - 1)];
     };
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int qi = (wave >> 1) * 64, qj = (wave & 1) * 64;   // this wave's quadrant
     const int jb = diag ? 0 : kTile;
     dv4 acc[4][4];
@@ -134,9 +144,21 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
             if (q >= nper) break;
             const int rr = srow + q * rstep;
             const bool row_ok = r + rr < r1 && chunk_ok;
+            if constexpr (std::is_same<LT, float>::value) {
+                float v[VE];
 #pragma unroll
-            for (int e = 0; e < VE; ++e)
-                xs[rr][lcol + e] = (row_ok && col0 + e < p.K) ? chunk_elem<DT>(raw[q], e, cs[e]) : 0.0;
+                for (int e = 0; e < VE; ++e) {
+                    const unsigned bits = DT == GLM_F32 ? raw[q][e]
+                                                       : ((raw[q][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) << 16;
+                    v[e] = (row_ok && col0 + e < p.K) ? __uint_as_float(bits) : 0.0f;
+                }
+#pragma unroll
+                for (int e = 0; e < VE; ++e) xs[rr][lcol + e] = v[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < VE; ++e)
+                    xs[rr][lcol + e] = (row_ok && col0 + e < p.K) ? chunk_elem<DT>(raw[q], e, cs[e]) : 0.0;
+            }
         }
         if (threadIdx.x < R) ws[threadIdx.x] = r + threadIdx.x < r1 ? wl : 0.0;
         __syncthreads();
@@ -149,14 +171,18 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
             double a[4], b[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                a[t] = wk * xs[kk][qi + 16 * t + (lane & 15)];
-                b[t] = xs[kk][jb + qj + 16 * t + (lane & 15)];
+                a[t] = wk * (double)xs[kk][qi + 16 * t + (lane & 15)];
+                b[t] = (double)xs[kk][jb + qj + 16 * t + (lane & 15)];
             }
+            // on a diagonal tile the 16 x 16 blocks wholly below the diagonal
+            // are skipped (the merge reads i <= j only there); the condition
+            // is wave-uniform
 #pragma unroll
             for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
                 for (int tb = 0; tb < 4; ++tb)
-                    acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+                    if (!diag || qi + 16 * ta <= qj + 16 * tb)
+                        acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
         }
     }
 
@@ -204,13 +230,17 @@ __global__ __launch_bounds__(kHT) void k_hess_merge(const double* __restrict__ p
 
 // Matrix-core throughput probe: 16 independent FP64 16x16x4 accumulators per
 // wave, `iters` rounds; the sum of the results is written (per lane) only so
-// that the work is kept.
+// that the work is kept.  The first round starts from zero inside the matrix
+// instruction: with the accumulators zeroed by moves the compiler kept them
+// in VGPRs between rounds and copied all 128 registers to and from AGPRs
+// around every round, which halved the matrix rate the probe saw.
 __global__ __launch_bounds__(kHT) void k_mfma_probe(double* __restrict__ sink, int iters, double seed) {
+    const double a = seed + threadIdx.x, b = seed - threadIdx.x;
     dv4 acc[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = dv4{0.0, 0.0, 0.0, 0.0};
-    const double a = seed + threadIdx.x, b = seed - threadIdx.x;
-    for (int it = 0; it < iters; ++it) {
+    for (int i = 0; i < 16; ++i)
+        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, dv4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+    for (int it = 1; it < iters; ++it) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
     }
@@ -246,8 +276,12 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
 
     const int ntile = (K + kTile - 1) / kTile;
     const int nup = ntile * (ntile + 1) / 2;
+    // Two blocks fit a compute unit (LDS and registers), so the grid fills
+    // the 2 x num_cu slots at most: rounding the chunk count up put one block
+    // past them (513 blocks at K = 256), and that block ran after all the
+    // others, nearly doubling the kernel's time.
     const int nchunk = (int)std::max<int64_t>(
-        1, std::min<int64_t>((2 * (int64_t)ctx->num_cu + nup - 1) / nup, (N + 31) / 32));
+        1, std::min<int64_t>(2 * (int64_t)ctx->num_cu / nup, (N + 31) / 32));
 
     // per-stream buffers: w (N), partials, tile list
     HessBuf& hb = ctx->hess[stream];

@@ -13,23 +13,16 @@ constexpr int WPB = 4;
 
 // R = 8 row slots per lane keeps the NB copies of beta and of the gradient
 // accumulators within the register file; instances with more than 32 values
-// of beta or gradient per lane (NB x columns per lane) are not built.  FP32
-// rows of 32 lanes with 8 vectors take 4 row slots instead, which fits two
-// waves per SIMD (255 registers) and runs 8 waves per block: 9-12 % faster
-// than 8 slots at one wave per SIMD.  (The other widths spill with 4 slots.)
+// of beta or gradient per lane (NB x columns per lane) are not built.  (With
+// FP64 coefficients and linear predictors, 4 slots and 8 waves per block no
+// longer fit two waves per SIMD: FP32 rows of 32 lanes with 8 vectors then
+// spilled to scratch and ran 144 us per vector over 2 GB against 125 with 4
+// vectors.)
 template <int DT, int LPR, int CPL, int NB>
 MultiInst minst() {
     constexpr int VE = 16 / glmk::ElemSize<DT>::v;
     if constexpr (NB * CPL * VE > 32) {
         return MultiInst{};
-    } else if constexpr (DT == glmk::DT_F32 && LPR == 32 && CPL == 1 && NB == 8) {
-        MultiInst m;
-        m.fn = reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 4, 8, NB>);
-        m.R = 4;
-        m.NB = NB;
-        m.fleet = reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 4, 8, NB>);
-        m.wpb = 8;
-        return m;
     } else {
         return MultiInst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 8, WPB, NB>), 8, NB,
                          reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 8, WPB, NB>)};
