@@ -269,7 +269,7 @@ __device__ __forceinline__ void tr_map(double u, unsigned yb, int fam, double& t
     const double yv = (double)(yb & 1u);
     const double e = exp_f64(-fabs(u));
     const double sp = fmax(u, 0.0) + log1p_unit(e);
-    const double inv = 1.0 / (1.0 + e);
+    const double inv = recip_1_8(1.0 + e);
     const double sig = u >= 0.0 ? inv : e * inv;
     t = yv * u - sp;
     r = yv - sig;
@@ -281,7 +281,7 @@ __device__ __forceinline__ void tr_map(double u, unsigned yb, int fam, double& t
 __device__ __forceinline__ double tr_weight(double u, int fam) {
     if (fam == 1) return exp_f64(u);
     const double e = exp_f64(-fabs(u));
-    const double inv = 1.0 / (1.0 + e);
+    const double inv = recip_1_8(1.0 + e);
     return e * inv * inv;
 }
 

@@ -16,6 +16,13 @@
 //                the same series, and m ln2 added with the split ln2 of exp;
 //                near x = 1 (m = 0) the result keeps its relative accuracy.
 //
+//   1 / x:       for x in [1, 8] (the denominators above and of the
+//                sigmoid): the hardware reciprocal estimate refined by two
+//                Newton-Raphson steps r <- r + r (1 - x r), each of which
+//                squares the relative error, instead of a full IEEE division
+//                (which also scales and fixes up operands these values never
+//                need).
+//
 // All are within a few units in the last place of the correctly rounded
 // value; NaN in gives NaN out.
 #pragma once
@@ -48,9 +55,18 @@ __device__ __forceinline__ double exp_f64(double x) {
     return ldexp(p, (int)k);
 }
 
+// 1 / x for x in [1, 8].
+__device__ __forceinline__ double recip_1_8(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // 2 atanh(zm1 / zp1) = log z for z = 1 + zm1 = zp1 - 1 in [sqrt(1/2), sqrt(2)).
 __device__ __forceinline__ double log_series(double zm1, double zp1) {
-    const double s = zm1 / zp1;
+    const double s = zm1 * recip_1_8(zp1);
     const double s2 = s * s;
     double q = 1.0 / 21.0;
     q = fma(q, s2, 1.0 / 19.0);
