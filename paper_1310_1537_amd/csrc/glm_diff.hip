@@ -148,7 +148,7 @@ __device__ __forceinline__ void load4(const void* col, int64_t n0, float s, doub
 // takes a ticket, costs that a grid of many small blocks would multiply.
 //
 // Rows are taken in groups of four (one vector load of the column, two of
-// u, one of y), two groups per loop trip with all loads issued first; the
+// u, one of y), several groups per loop trip with all loads issued first; the
 // N mod 4 rows after the last group are taken one at a time.  The vector
 // loads need the column 4-element aligned, u 16-byte and y 4-byte aligned
 // (checked by the host, which otherwise launches with vec = false).
@@ -181,25 +181,34 @@ __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
         const int64_t ng = p.N >> 2;
         const dv2* u2 = reinterpret_cast<const dv2*>(p.u);
         const unsigned* y4 = reinterpret_cast<const unsigned*>(p.y);
-        for (int64_t g = gtid; g < ng; g += 2 * stride) {
-            const int64_t g2 = g + stride;
-            const bool two = g2 < ng;
-            const int64_t gb = two ? g2 : g;   // a valid address either way
-            double xa[4], xb[4];
-            load4<DT>(p.col, 4 * g, p.s, xa);
-            load4<DT>(p.col, 4 * gb, p.s, xb);
-            const dv2 ua0 = u2[2 * g], ua1 = u2[2 * g + 1];
-            const dv2 ub0 = u2[2 * gb], ub1 = u2[2 * gb + 1];
-            const unsigned ya = y4[g], yb = y4[gb];
-            add_row(xa[0], ua0.x, ya & 0xFFu);
-            add_row(xa[1], ua0.y, (ya >> 8) & 0xFFu);
-            add_row(xa[2], ua1.x, (ya >> 16) & 0xFFu);
-            add_row(xa[3], ua1.y, ya >> 24);
-            if (two) {
-                add_row(xb[0], ub0.x, yb & 0xFFu);
-                add_row(xb[1], ub0.y, (yb >> 8) & 0xFFu);
-                add_row(xb[2], ub1.x, (yb >> 16) & 0xFFu);
-                add_row(xb[3], ub1.y, yb >> 24);
+        // GT groups per trip, every load of the trip issued before the first
+        // row is added (one memory latency per trip; with one step size a
+        // trip of four covers this thread's share of 4M rows; wider forms
+        // keep two, which fit the registers)
+        constexpr int GT = DMAX == 1 && DT != GLM_F64 ? 4 : 2;
+        for (int64_t g = gtid; g < ng; g += GT * stride) {
+            double x[GT][4];
+            dv2 ua[GT][2];
+            unsigned yy[GT];
+            bool ok[GT];
+#pragma unroll
+            for (int q = 0; q < GT; ++q) {
+                const int64_t gq = g + q * stride;
+                ok[q] = gq < ng;
+                const int64_t gv = ok[q] ? gq : g;   // a valid address either way
+                load4<DT>(p.col, 4 * gv, p.s, x[q]);
+                ua[q][0] = u2[2 * gv];
+                ua[q][1] = u2[2 * gv + 1];
+                yy[q] = y4[gv];
+            }
+#pragma unroll
+            for (int q = 0; q < GT; ++q) {
+                if (ok[q]) {
+                    add_row(x[q][0], ua[q][0].x, yy[q] & 0xFFu);
+                    add_row(x[q][1], ua[q][0].y, (yy[q] >> 8) & 0xFFu);
+                    add_row(x[q][2], ua[q][1].x, (yy[q] >> 16) & 0xFFu);
+                    add_row(x[q][3], ua[q][1].y, yy[q] >> 24);
+                }
             }
         }
         n_scalar = ng << 2;
