@@ -11,17 +11,20 @@
 // Three launches in stream order:
 //   1. the fused f+g kernel, which also writes each row's w_n (N doubles);
 //   2. k_hess: the K x K output is cut into 128 x 128 tiles, of which the
-//      upper triangle (tile row <= tile column) is computed; the rows are cut
-//      into S chunks; block (tile, chunk) stages 32 rows of the tile's column
-//      ranges (and w) into LDS as doubles and its four waves each accumulate
-//      a 64 x 64 quadrant with 4 x 4 MFMA blocks, four rows per instruction,
-//      and write the block's partial tile;
-//   3. k_hess_merge: one thread per tile entry adds the S partials in chunk
-//      order and writes the entry and its mirror image, minus prec on the
-//      diagonal.
+//      upper triangle (tile row <= tile column) is computed; each tile's rows
+//      are cut into chunks (more for off-diagonal tiles, whose work per row
+//      is larger); block (tile, chunk) stages 32 rows of the tile's column
+//      ranges (and w) into LDS and its four waves accumulate 16 x 16 MFMA
+//      blocks, four rows per instruction: on an off-diagonal tile a 64 x 64
+//      quadrant (4 x 4 blocks) each, on a diagonal tile 9 of the 36 blocks on
+//      or above the diagonal each; the block writes its partial tile;
+//   3. k_hess_merge: one thread per tile entry adds the tile's partials in
+//      chunk order and writes the entry and its mirror image, minus prec on
+//      the diagonal.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -44,9 +47,9 @@ struct HessParams {
     const double* w;          // N row weights
     int64_t N;
     int K;
-    int nchunk;               // row chunks
-    const int2* tiles;        // (tile row, tile column) of each upper-triangle tile
-    double* partials;         // ntiles_upper x nchunk x kTile x kTile
+    const int4* tiles;        // per upper-triangle tile: tile row, tile column, first block, chunks
+    const int2* blocks;       // per block: tile, chunk
+    double* partials;         // blocks x kTile x kTile
 };
 
 // Element e of a 16-byte chunk of stored elements, as a double.
@@ -79,13 +82,13 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
     constexpr int CR = kTile / VE;              // chunks per column range
     constexpr int NPMAX = R * 2 * CR / kHT;     // chunks per thread (off-diagonal tile)
     const unsigned char* X = static_cast<const unsigned char*>(p.X);
-    const int tile = blockIdx.x / p.nchunk;
-    const int chunk = blockIdx.x % p.nchunk;
-    const int2 tc = p.tiles[tile];
+    const int2 bt = p.blocks[blockIdx.x];
+    const int4 tc = p.tiles[bt.x];
+    const int chunk = bt.y, nch = tc.w;
     const int i0 = tc.x * kTile, j0 = tc.y * kTile;
     const bool diag = tc.x == tc.y;
-    const int64_t r0 = p.N * chunk / p.nchunk;
-    const int64_t r1 = p.N * (chunk + 1) / p.nchunk;
+    const int64_t r0 = p.N * chunk / nch;
+    const int64_t r1 = p.N * (chunk + 1) / nch;
 
     // xs[r][c]: c < kTile the i-range, c >= kTile the j-range (off-diagonal
     // tiles).  The row stride is 16 doubles past a multiple of 32 (64 banks of
@@ -128,16 +131,9 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int qi = (wave >> 1) * 64, qj = (wave & 1) * 64;   // this wave's quadrant
-    const int jb = diag ? 0 : kTile;
-    dv4 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = dv4{0.0, 0.0, 0.0, 0.0};
 
-    if (r0 < r1) fetch(r0);
-    for (int64_t r = r0; r < r1; r += R) {
+    // Stages rows r .. r + R - 1 of the chunk into xs / ws (every thread).
+    auto stage = [&](int64_t r) {
         __syncthreads();   // the previous step's MFMA reads of xs are done
 #pragma unroll
         for (int q = 0; q < NPMAX; ++q) {
@@ -163,58 +159,103 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
         if (threadIdx.x < R) ws[threadIdx.x] = r + threadIdx.x < r1 ? wl : 0.0;
         __syncthreads();
         if (r + R < r1) fetch(r + R);
-#pragma unroll
-        for (int k0 = 0; k0 < R; k0 += 4) {
-            // A[i][k] = w_k x_k,(i0+i), B[k][j] = x_k,(j0+j); lane: i or j = lane % 16, k = lane / 16
-            const int kk = k0 + (lane >> 4);
-            const double wk = ws[kk];
-            double a[4], b[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                a[t] = wk * (double)xs[kk][qi + 16 * t + (lane & 15)];
-                b[t] = (double)xs[kk][jb + qj + 16 * t + (lane & 15)];
-            }
-            // on a diagonal tile the 16 x 16 blocks wholly below the diagonal
-            // are skipped (the merge reads i <= j only there); the condition
-            // is wave-uniform
-#pragma unroll
-            for (int ta = 0; ta < 4; ++ta)
-#pragma unroll
-                for (int tb = 0; tb < 4; ++tb)
-                    if (!diag || qi + 16 * ta <= qj + 16 * tb)
-                        acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
-        }
-    }
+    };
 
-    // partial tile: D[row][col] of a 16 x 16 block sits in lane col + 16 (row % 4), item row / 4
+    // partial tile of this block: D[row][col] of a 16 x 16 block sits in lane
+    // col + 16 (row % 4), item row / 4
     double* part = p.partials + (int64_t)blockIdx.x * kTile * kTile;
+    auto store_block = [&](int bi, int bj, const dv4& d) {
 #pragma unroll
-    for (int ta = 0; ta < 4; ++ta)
+        for (int q = 0; q < 4; ++q)
+            part[(16 * bi + (lane >> 4) + 4 * q) * kTile + 16 * bj + (lane & 15)] = d[q];
+    };
+
+    if (diag) {
+        // The 36 blocks (I, J), I <= J, of the 8 x 8 grid: wave w takes row w
+        // (J = w .. 7, 8 - w blocks) and row 7 - w (J = 7 - w .. 7, w + 1
+        // blocks), 9 in all, so the four waves (and their SIMDs) carry equal
+        // matrix work.  Slot s's (I, J) is wave-uniform.
+        int bi[9], bj[9];
 #pragma unroll
-        for (int tb = 0; tb < 4; ++tb)
+        for (int s2 = 0; s2 < 9; ++s2) {
+            const bool first = s2 < 8 - wave;
+            bi[s2] = first ? wave : 7 - wave;
+            bj[s2] = first ? wave + s2 : 7 - wave + (s2 - (8 - wave));
+        }
+        dv4 acc[9];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i = qi + 16 * ta + (lane >> 4) + 4 * q;
-                const int j = qj + 16 * tb + (lane & 15);
-                part[i * kTile + j] = acc[ta][tb][q];
+        for (int s2 = 0; s2 < 9; ++s2) acc[s2] = dv4{0.0, 0.0, 0.0, 0.0};
+        if (r0 < r1) fetch(r0);
+        for (int64_t r = r0; r < r1; r += R) {
+            stage(r);
+#pragma unroll
+            for (int k0 = 0; k0 < R; k0 += 4) {
+                const int kk = k0 + (lane >> 4);
+                const double wk = ws[kk];
+                // the row w blocks share A (I = w); so do the row 7 - w blocks
+                const double a1 = wk * (double)xs[kk][16 * wave + (lane & 15)];
+                const double a2 = wk * (double)xs[kk][16 * (7 - wave) + (lane & 15)];
+#pragma unroll
+                for (int s2 = 0; s2 < 9; ++s2) {
+                    const double b = (double)xs[kk][16 * bj[s2] + (lane & 15)];
+                    acc[s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2 < 8 - wave ? a1 : a2, b, acc[s2],
+                                                                  0, 0, 0);
+                }
             }
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 9; ++s2) store_block(bi[s2], bj[s2], acc[s2]);
+    } else {
+        const int qi = (wave >> 1) * 64, qj = (wave & 1) * 64;   // this wave's quadrant
+        dv4 acc[4][4];
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) acc[ta][tb] = dv4{0.0, 0.0, 0.0, 0.0};
+        if (r0 < r1) fetch(r0);
+        for (int64_t r = r0; r < r1; r += R) {
+            stage(r);
+#pragma unroll
+            for (int k0 = 0; k0 < R; k0 += 4) {
+                // A[i][k] = w_k x_k,(i0+i), B[k][j] = x_k,(j0+j); lane: i or j = lane % 16, k = lane / 16
+                const int kk = k0 + (lane >> 4);
+                const double wk = ws[kk];
+                double a[4], b[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    a[t] = wk * (double)xs[kk][qi + 16 * t + (lane & 15)];
+                    b[t] = (double)xs[kk][kTile + qj + 16 * t + (lane & 15)];
+                }
+#pragma unroll
+                for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < 4; ++tb)
+                        acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) store_block(qi / 16 + ta, qj / 16 + tb, acc[ta][tb]);
+    }
 }
 
 // H entries from the partials: each thread sums one tile entry over the
 // chunks in chunk order; on a diagonal tile only i <= j is taken and mirrored,
 // so H is exactly symmetric.
 __global__ __launch_bounds__(kHT) void k_hess_merge(const double* __restrict__ partials,
-                                                    const int2* __restrict__ tiles, int nchunk,
+                                                    const int4* __restrict__ tiles,
                                                     int K, double prec, double* __restrict__ H) {
     const int64_t e_all = (int64_t)blockIdx.x * kHT + threadIdx.x;
     const int tile = (int)(e_all / (kTile * kTile));
     const int e = (int)(e_all % (kTile * kTile));
-    const int2 tc = tiles[tile];
+    const int4 tc = tiles[tile];
+    const int nchunk = tc.w;
     const int i = e / kTile, j = e % kTile;
     const int gi = tc.x * kTile + i, gj = tc.y * kTile + j;
     const bool diag = tc.x == tc.y;
     if (gi >= K || gj >= K || (diag && i > j)) return;
-    const double* base = partials + (int64_t)tile * nchunk * kTile * kTile + e;
+    const double* base = partials + (int64_t)tc.z * kTile * kTile + e;
     double s = 0.0;
     for (int c = 0; c < nchunk; c += 8) {
         double v[8];
@@ -276,26 +317,39 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
 
     const int ntile = (K + kTile - 1) / kTile;
     const int nup = ntile * (ntile + 1) / 2;
-    // Two blocks fit a compute unit (LDS and registers), so the grid fills
-    // the 2 x num_cu slots at most: rounding the chunk count up put one block
-    // past them (513 blocks at K = 256), and that block ran after all the
-    // others, nearly doubling the kernel's time.
-    const int nchunk = (int)std::max<int64_t>(
-        1, std::min<int64_t>(2 * (int64_t)ctx->num_cu / nup, (N + 31) / 32));
+    // Chunks per tile, weighted by the matrix work per row of one of its
+    // blocks (16 blocks of 16 x 16 per wave on an off-diagonal tile, 9 on a
+    // diagonal one), so that the blocks take about equal time; the grid fills
+    // the two-blocks-per-CU slots at most (a block past them runs after all
+    // the others, nearly doubling the kernel's time).
+    const int64_t slots = 2 * (int64_t)ctx->num_cu;
+    const int64_t maxch = std::max<int64_t>(1, (N + 31) / 32);
+    const double wsum = 9.0 * ntile + 16.0 * (nup - ntile);
+    std::vector<int> tl;   // per tile: row, column, first block, chunks
+    std::vector<int> bl;   // per block: tile, chunk
+    for (int a = 0, t = 0; a < ntile; ++a)
+        for (int b = a; b < ntile; ++b, ++t) {
+            const double wt = a == b ? 9.0 : 16.0;
+            const int nch = (int)std::min<int64_t>(
+                maxch, std::max<int64_t>(1, (int64_t)std::floor((double)slots * wt / wsum)));
+            tl.insert(tl.end(), {a, b, (int)(bl.size() / 2), nch});
+            for (int c = 0; c < nch; ++c) bl.insert(bl.end(), {t, c});
+        }
+    const int nblk = (int)(bl.size() / 2);
 
-    // per-stream buffers: w (N), partials, tile list
+    // per-stream buffers: w (N), partials (one tile per block), tile and block tables
     HessBuf& hb = ctx->hess[stream];
-    const size_t need = (size_t)std::max<int64_t>(N, 1) + (size_t)nup * nchunk * kTile * kTile +
-                        (size_t)nup + 1;   // doubles (the tile list follows)
-    if (hb.cap < need || hb.ntick < (size_t)nup) {
+    const size_t need = (size_t)std::max<int64_t>(N, 1) + (size_t)nblk * kTile * kTile;   // doubles
+    const size_t nint = tl.size() + bl.size();
+    if (hb.cap < need || hb.ntick < nint) {
         if (hb.buf) {
             GLM_HIP_CHECK(hipStreamSynchronize(s));
             GLM_HIP_CHECK(hipFree(hb.buf));
             hb = HessBuf{};
         }
         const size_t cap = need * 5 / 4 + 1024;
-        const size_t nt = std::max<size_t>((size_t)nup * 2, 64);
-        if (hipMalloc((void**)&hb.buf, cap * sizeof(double) + nt * sizeof(int2)) != hipSuccess)
+        const size_t nt = std::max<size_t>(nint * 2, 256);
+        if (hipMalloc((void**)&hb.buf, cap * sizeof(double) + nt * sizeof(int)) != hipSuccess)
             GLM_FAIL(GLM_ENOMEM, "glm_logpost_grad_hess: device allocation failed");
         hb.cap = cap;
         hb.ntick = nt;
@@ -304,16 +358,13 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
     }
     double* w = hb.buf;
     double* partials = hb.buf + std::max<int64_t>(N, 1);
-    if (hb.tiles_for != ntile) {
-        std::vector<int> t;
-        for (int a = 0; a < ntile; ++a)
-            for (int b = a; b < ntile; ++b) {
-                t.push_back(a);
-                t.push_back(b);
-            }
+    if (hb.tiles_for != ntile || hb.tiles_rows != maxch) {
+        std::vector<int> t(tl);
+        t.insert(t.end(), bl.begin(), bl.end());
         GLM_HIP_CHECK(hipMemcpyAsync(hb.tiles, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice, s));
         GLM_HIP_CHECK(hipStreamSynchronize(s));
         hb.tiles_for = ntile;
+        hb.tiles_rows = maxch;
     }
 
     // 1. f, g and the row weights
@@ -334,10 +385,10 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
     p.w = w;
     p.N = N;
     p.K = K;
-    p.nchunk = nchunk;
-    p.tiles = reinterpret_cast<const int2*>(hb.tiles);
+    p.tiles = reinterpret_cast<const int4*>(hb.tiles);
+    p.blocks = reinterpret_cast<const int2*>(hb.tiles + tl.size());
     p.partials = partials;
-    const dim3 grid((unsigned)(nup * nchunk));
+    const dim3 grid((unsigned)nblk);
     switch (ds.d.dtype) {
     case GLM_F64: hipLaunchKernelGGL(k_hess<GLM_F64>, grid, dim3(kHT), 0, s, p); break;
     case GLM_F32: hipLaunchKernelGGL(k_hess<GLM_F32>, grid, dim3(kHT), 0, s, p); break;
@@ -346,7 +397,7 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
     }
     GLM_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_hess_merge, dim3((unsigned)((int64_t)nup * kTile * kTile / kHT)), dim3(kHT), 0,
-                       s, partials, p.tiles, nchunk, K, prior->prec, H);
+                       s, partials, p.tiles, K, prior->prec, H);
     GLM_HIP_CHECK(hipGetLastError());
     return GLM_OK;
 }

@@ -92,14 +92,15 @@ struct SamplerBuf {
     size_t cap = 0;        // doubles
 };
 
-// Hessian buffers of one stream: row weights, tile partials and the tile
-// list.
+// Hessian buffers of one stream: row weights, block partials and the tile
+// and block tables.
 struct HessBuf {
     double* buf = nullptr;
-    size_t cap = 0;            // doubles before the tile list
-    size_t ntick = 0;          // tile-list capacity (pairs)
-    int* tiles = nullptr;      // (tile row, tile column) pairs
-    int tiles_for = -1;        // tiles per side the list was built for
+    size_t cap = 0;            // doubles before the tables
+    size_t ntick = 0;          // table capacity (ints)
+    int* tiles = nullptr;      // per tile (row, column, first block, chunks), then per block (tile, chunk)
+    int tiles_for = -1;        // tiles per side the tables were built for
+    int64_t tiles_rows = -1;   // and the chunk cap ((N + 31) / 32) they used
 };
 
 struct GroupSet;   // defined by the batched entry point
