@@ -18,14 +18,28 @@ constexpr int WPB = 4;
 // longer fit two waves per SIMD: FP32 rows of 32 lanes with 8 vectors then
 // spilled to scratch and ran 144 us per vector over 2 GB against 125 with 4
 // vectors.)
+//
+// Two geometries take 4 row slots instead, where the tile then fits in FP64
+// once for all vectors (times over 2 GB):
+//  - FP32 rows of 512 columns (64 lanes x 2 chunks) with 2 vectors, with a
+//    ring of 3 tiles: 309 us against 331 with 8 slots (with 4 vectors 8 slots
+//    stay faster, 447 against 480 us);
+//  - BF16 rows of at most 32 columns (one chunk on at most 4 lanes): a pass
+//    of 4 vectors 2491 against 2877 us at 8 columns, 1158 against 1333 at 32.
+//    (At 128 and 512 columns 8 slots stay faster: 508 against 556 us and 486
+//    against 553 for 2 vectors.)
 template <int DT, int LPR, int CPL, int NB>
 MultiInst minst() {
     constexpr int VE = 16 / glmk::ElemSize<DT>::v;
+    constexpr bool F32_WIDE = DT == glmk::DT_F32 && LPR == 64 && CPL == 2 && NB == 2;
+    constexpr bool BF16_NARROW = DT == glmk::DT_BF16 && CPL == 1 && LPR <= 4;
+    constexpr int R = F32_WIDE || BF16_NARROW ? 4 : 8;
+    constexpr int NBUF = F32_WIDE ? 3 : 2;
     if constexpr (NB * CPL * VE > 32) {
         return MultiInst{};
     } else {
-        return MultiInst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, 8, WPB, NB>), 8, NB,
-                         reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, 8, WPB, NB>)};
+        return MultiInst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, R, WPB, NB, NBUF>), R,
+                         NB, reinterpret_cast<const void*>(&glmk::fg_fleet<DT, LPR, CPL, R, WPB, NB, NBUF>)};
     }
 }
 
