@@ -193,8 +193,12 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
                 const int kk = k0 + (lane >> 4);
                 const double wk = ws[kk];
                 // the row w blocks share A (I = w); so do the row 7 - w blocks
-                const double a1 = wk * (double)xs[kk][16 * wave + (lane & 15)];
-                const double a2 = wk * (double)xs[kk][16 * (7 - wave) + (lane & 15)];
+                // (both formed once: the empty asm keeps the compiler from
+                // selecting between the raw values per block and converting
+                // and scaling A nine times)
+                double a1 = wk * (double)xs[kk][16 * wave + (lane & 15)];
+                double a2 = wk * (double)xs[kk][16 * (7 - wave) + (lane & 15)];
+                asm volatile("" : "+v"(a1), "+v"(a2));
 #pragma unroll
                 for (int s2 = 0; s2 < 9; ++s2) {
                     const double b = (double)xs[kk][16 * bj[s2] + (lane & 15)];
@@ -317,19 +321,23 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
 
     const int ntile = (K + kTile - 1) / kTile;
     const int nup = ntile * (ntile + 1) / 2;
-    // Chunks per tile, weighted by the matrix work per row of one of its
-    // blocks (16 blocks of 16 x 16 per wave on an off-diagonal tile, 9 on a
-    // diagonal one), so that the blocks take about equal time; the grid fills
+    // Chunks per tile, weighted by the time per row of one of its blocks, so
+    // that the blocks take about equal time: a diagonal tile's wave has 9
+    // blocks of 16 x 16 against 16 on an off-diagonal one, but reads an
+    // operand per matrix instruction where the other reads one per two, and
+    // its rows took 0.70 of the time of an off-diagonal tile's (FP32 rows of
+    // 256 columns, 512 blocks over 4M rows per tile kind); the grid fills
     // the two-blocks-per-CU slots at most (a block past them runs after all
     // the others, nearly doubling the kernel's time).
     const int64_t slots = 2 * (int64_t)ctx->num_cu;
     const int64_t maxch = std::max<int64_t>(1, (N + 31) / 32);
-    const double wsum = 9.0 * ntile + 16.0 * (nup - ntile);
+    constexpr double kDiagWeight = 0.70, kOffWeight = 1.0;
+    const double wsum = kDiagWeight * ntile + kOffWeight * (nup - ntile);
     std::vector<int> tl;   // per tile: row, column, first block, chunks
     std::vector<int> bl;   // per block: tile, chunk
     for (int a = 0, t = 0; a < ntile; ++a)
         for (int b = a; b < ntile; ++b, ++t) {
-            const double wt = a == b ? 9.0 : 16.0;
+            const double wt = a == b ? kDiagWeight : kOffWeight;
             const int nch = (int)std::min<int64_t>(
                 maxch, std::max<int64_t>(1, (int64_t)std::floor((double)slots * wt / wsum)));
             tl.insert(tl.end(), {a, b, (int)(bl.size() / 2), nch});
