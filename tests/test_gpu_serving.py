@@ -75,6 +75,25 @@ def test_multi_per_vector_means_and_bf16(ctx):
     glm.glm_dataset_unregister(ctx, ds)
 
 
+@pytest.mark.parametrize("K", [8, 16, 24, 32])
+@pytest.mark.parametrize("nb", [3, 4, 11])
+def test_multi_bf16_short_rows(ctx, K, nb):
+    """BF16 rows of at most 32 columns (one chunk on at most four lanes, the
+    instances with four row slots; at K = 24 the fourth lane holds no column)
+    against the oracle on the codes, at beta and at beta = 0."""
+    X, y, bt = _data(20_011, K, 3 * K + nb)
+    Q = oracle.quantize_bf16(X)
+    B = _betas(bt, nb, 9)
+    Qd, yd = to_dev(Q), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Qd, yd, dtype=glm.GLM_BF16))
+    for Bc in (B, np.zeros_like(B)):
+        o = _multi(ctx, ds, Bc, K)
+        for b in range(nb):
+            _check(o[b, 0], o[b, 1:], oracle.decode_bf16(Q), y, Bc[b], 0.01, storage="bf16", Xo=Q,
+                   okw={"dtype": "bf16"})
+    glm.glm_dataset_unregister(ctx, ds)
+
+
 def test_multi_result_independent_of_companions(ctx):
     """Slot 0 of a pass gives the same bits whatever the other slots hold."""
     X, y, bt = _data(30_000, 128, 4)
