@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
     // they are all in flight at once
     uv4 raw[NPMAX];
     double wl = 0.0;
-    auto fetch = [&](int64_t r) {
+    auto fetch = [&](int64_t r) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < NPMAX; ++q) {
             const int64_t row = min(r + srow + q * rstep, r1 - 1);
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     // Stages rows r .. r + R - 1 of the chunk into xs / ws (every thread).
-    auto stage = [&](int64_t r) {
+    auto stage = [&](int64_t r) __attribute__((always_inline)) {
         __syncthreads();   // the previous step's MFMA reads of xs are done
 #pragma unroll
         for (int q = 0; q < NPMAX; ++q) {
@@ -164,51 +164,60 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
     // partial tile of this block: D[row][col] of a 16 x 16 block sits in lane
     // col + 16 (row % 4), item row / 4
     double* part = p.partials + (int64_t)blockIdx.x * kTile * kTile;
-    auto store_block = [&](int bi, int bj, const dv4& d) {
+    auto store_block = [&](int bi, int bj, const dv4& d) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             part[(16 * bi + (lane >> 4) + 4 * q) * kTile + 16 * bj + (lane & 15)] = d[q];
     };
 
     if (diag) {
-        // The 36 blocks (I, J), I <= J, of the 8 x 8 grid: wave w takes row w
-        // (J = w .. 7, 8 - w blocks) and row 7 - w (J = 7 - w .. 7, w + 1
+        // The 36 blocks (I, J), I <= J, of the 8 x 8 grid: wave W takes row W
+        // (J = W .. 7, 8 - W blocks) and row 7 - W (J = 7 - W .. 7, W + 1
         // blocks), 9 in all, so the four waves (and their SIMDs) carry equal
-        // matrix work.  Slot s's (I, J) is wave-uniform.
-        int bi[9], bj[9];
+        // matrix work.  The loop is compiled once per wave index, so that the
+        // compiler knows which blocks share an operand: the row 7 - W blocks'
+        // columns are a subset of the row W blocks' (W <= 3), and a wave reads
+        // 2 A and 8 - W B operands per four rows for its 9 matrix
+        // instructions (with the wave index known only at run time it read
+        // and converted one B per instruction and chose A per instruction).
+        auto run = [&](auto wc) __attribute__((always_inline)) {
+            constexpr int W = decltype(wc)::value;
+            constexpr int NA = 8 - W;            // row W blocks
+            dv4 acc[9];
 #pragma unroll
-        for (int s2 = 0; s2 < 9; ++s2) {
-            const bool first = s2 < 8 - wave;
-            bi[s2] = first ? wave : 7 - wave;
-            bj[s2] = first ? wave + s2 : 7 - wave + (s2 - (8 - wave));
-        }
-        dv4 acc[9];
+            for (int s2 = 0; s2 < 9; ++s2) acc[s2] = dv4{0.0, 0.0, 0.0, 0.0};
+            if (r0 < r1) fetch(r0);
+            for (int64_t r = r0; r < r1; r += R) {
+                stage(r);
 #pragma unroll
-        for (int s2 = 0; s2 < 9; ++s2) acc[s2] = dv4{0.0, 0.0, 0.0, 0.0};
-        if (r0 < r1) fetch(r0);
-        for (int64_t r = r0; r < r1; r += R) {
-            stage(r);
+                for (int k0 = 0; k0 < R; k0 += 4) {
+                    const int kk = k0 + (lane >> 4);
+                    const double wk = ws[kk];
+                    const double a1 = wk * (double)xs[kk][16 * W + (lane & 15)];
+                    const double a2 = wk * (double)xs[kk][16 * (7 - W) + (lane & 15)];
+                    double bv[NA];   // B of block column W + s
 #pragma unroll
-            for (int k0 = 0; k0 < R; k0 += 4) {
-                const int kk = k0 + (lane >> 4);
-                const double wk = ws[kk];
-                // the row w blocks share A (I = w); so do the row 7 - w blocks
-                // (both formed once: the empty asm keeps the compiler from
-                // selecting between the raw values per block and converting
-                // and scaling A nine times)
-                double a1 = wk * (double)xs[kk][16 * wave + (lane & 15)];
-                double a2 = wk * (double)xs[kk][16 * (7 - wave) + (lane & 15)];
-                asm volatile("" : "+v"(a1), "+v"(a2));
+                    for (int s = 0; s < NA; ++s) bv[s] = (double)xs[kk][16 * (W + s) + (lane & 15)];
 #pragma unroll
-                for (int s2 = 0; s2 < 9; ++s2) {
-                    const double b = (double)xs[kk][16 * bj[s2] + (lane & 15)];
-                    acc[s2] = __builtin_amdgcn_mfma_f64_16x16x4f64(s2 < 8 - wave ? a1 : a2, b, acc[s2],
-                                                                  0, 0, 0);
+                    for (int s = 0; s < NA; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[s], acc[s], 0, 0, 0);
+#pragma unroll
+                    for (int t = 0; t <= W; ++t)
+                        acc[NA + t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bv[7 - 2 * W + t],
+                                                                          acc[NA + t], 0, 0, 0);
                 }
             }
-        }
 #pragma unroll
-        for (int s2 = 0; s2 < 9; ++s2) store_block(bi[s2], bj[s2], acc[s2]);
+            for (int s = 0; s < NA; ++s) store_block(W, W + s, acc[s]);
+#pragma unroll
+            for (int t = 0; t <= W; ++t) store_block(7 - W, 7 - W + t, acc[NA + t]);
+        };
+        switch (wave) {
+        case 0: run(std::integral_constant<int, 0>()); break;
+        case 1: run(std::integral_constant<int, 1>()); break;
+        case 2: run(std::integral_constant<int, 2>()); break;
+        default: run(std::integral_constant<int, 3>()); break;
+        }
     } else {
         const int qi = (wave >> 1) * 64, qj = (wave & 1) * 64;   // this wave's quadrant
         dv4 acc[4][4];
@@ -323,15 +332,15 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
     const int nup = ntile * (ntile + 1) / 2;
     // Chunks per tile, weighted by the time per row of one of its blocks, so
     // that the blocks take about equal time: a diagonal tile's wave has 9
-    // blocks of 16 x 16 against 16 on an off-diagonal one, but reads an
-    // operand per matrix instruction where the other reads one per two, and
-    // its rows took 0.70 of the time of an off-diagonal tile's (FP32 rows of
-    // 256 columns, 512 blocks over 4M rows per tile kind); the grid fills
+    // blocks of 16 x 16 against 16 on an off-diagonal one, but reads up to
+    // 10 operands per four rows where the other reads 8, and its rows took
+    // 0.60 of the time of an off-diagonal tile's (FP32 rows of 256 columns,
+    // 512 blocks over 4M rows per tile kind); the grid fills
     // the two-blocks-per-CU slots at most (a block past them runs after all
     // the others, nearly doubling the kernel's time).
     const int64_t slots = 2 * (int64_t)ctx->num_cu;
     const int64_t maxch = std::max<int64_t>(1, (N + 31) / 32);
-    constexpr double kDiagWeight = 0.70, kOffWeight = 1.0;
+    constexpr double kDiagWeight = 0.60, kOffWeight = 1.0;
     const double wsum = kDiagWeight * ntile + kOffWeight * (nup - ntile);
     std::vector<int> tl;   // per tile: row, column, first block, chunks
     std::vector<int> bl;   // per block: tile, chunk
