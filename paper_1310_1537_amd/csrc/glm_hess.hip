@@ -36,6 +36,7 @@ namespace {
 
 constexpr int kTile = 128;    // output tile edge
 constexpr int kHT = 256;      // threads per block (4 waves)
+constexpr int kRsrcWord3 = 0x00020000;   // buffer descriptor word 3, raw (untyped) buffers
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
 typedef unsigned uv4 __attribute__((ext_vector_type(4)));
@@ -253,6 +254,147 @@ __global__ __launch_bounds__(kHT) void k_hess(HessParams p) {
     }
 }
 
+// The same work for FP32 rows, with the rows loaded straight into LDS
+// (buffer_load ... lds, 16 bytes per lane; lane l's bytes land at the LDS
+// address + 16 l) into two buffers: the loads of the next R rows are issued
+// at the start of a step and waited for at its end, so a step costs the
+// matrix loop, a handful of load instructions and one barrier, and no
+// thread converts or stores anything.  One load instruction per row and
+// wave: lanes 0-31 bring the tile's row range (128 floats), lanes 32-63 its
+// column range; on a diagonal tile lanes 32-63 are out of range and write
+// zeros into the unused half.  Each step's buffer resource covers only its
+// valid rows, so rows past the chunk's end come in as zeros.  Columns past K
+// are not zeroed: they feed only entries (i, j) with i >= K or j >= K, which
+// the merge drops.  The partials are bitwise those of k_hess<GLM_F32> (the
+// same operands in the same order).
+__global__ __launch_bounds__(kHT) void k_hess_lds(HessParams p) {
+    constexpr int R = 32;                        // rows per step
+    constexpr int XS = 2 * kTile + 16;           // row stride (floats), as in k_hess
+    __shared__ float xs[2][R][XS];
+    __shared__ double ws[2][R];
+    const int2 bt = p.blocks[blockIdx.x];
+    const int4 tc = p.tiles[bt.x];
+    const int chunk = bt.y, nch = tc.w;
+    const int i0 = tc.x * kTile, j0 = tc.y * kTile;
+    const bool diag = tc.x == tc.y;
+    const int64_t r0 = p.N * chunk / nch;
+    const int64_t r1 = p.N * (chunk + 1) / nch;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned char* X = static_cast<const unsigned char*>(p.X);
+    const uint32_t ldb = (uint32_t)(p.ldx * 4);   // row pitch in bytes
+    const uint32_t voff = lane < 32 ? (uint32_t)(i0 + 4 * lane) * 4u
+                                    : (diag ? 0x7FFFFFF0u : (uint32_t)(j0 + 4 * (lane - 32)) * 4u);
+    // rows r .. r + R - 1 (those before r1) into buffer b: wave w loads rows
+    // 8w .. 8w + 7, wave 0 also the R weights (4 bytes per lane)
+    auto issue = [&](int64_t r, int b) __attribute__((always_inline)) {
+        const int64_t nv = min((int64_t)R, r1 - r);
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(X + r * (int64_t)ldb), 0, (int)(nv * ldb), kRsrcWord3);
+#pragma unroll
+        for (int q = 0; q < R / 4; ++q) {
+            const int rr = wave * (R / 4) + q;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rx, (__attribute__((address_space(3))) void*)&xs[b][rr][0], 16, (int)voff,
+                (int)(rr * ldb), 0, 0);
+        }
+        if (wave == 0) {
+            const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(p.w + r), 0, (int)(nv * 8), kRsrcWord3);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rw, (__attribute__((address_space(3))) void*)&ws[b][0], 4, lane * 4, 0, 0, 0);
+        }
+    };
+    // this wave's loads landed, then everyone's
+    auto settle = [&]() __attribute__((always_inline)) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    };
+    double* part = p.partials + (int64_t)blockIdx.x * kTile * kTile;
+    auto store_block = [&](int bi, int bj, const dv4& d) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            part[(16 * bi + (lane >> 4) + 4 * q) * kTile + 16 * bj + (lane & 15)] = d[q];
+    };
+    const int64_t nsteps = r1 > r0 ? (r1 - r0 + R - 1) / R : 0;
+    if (nsteps > 0) issue(r0, 0);
+    settle();
+    if (diag) {
+        // blocks and operand sharing as in k_hess
+        auto run = [&](auto wc) __attribute__((always_inline)) {
+            constexpr int W = decltype(wc)::value;
+            constexpr int NA = 8 - W;
+            dv4 acc[9];
+#pragma unroll
+            for (int s2 = 0; s2 < 9; ++s2) acc[s2] = dv4{0.0, 0.0, 0.0, 0.0};
+            for (int64_t st = 0; st < nsteps; ++st) {
+                const int b = (int)(st & 1);
+                if (st + 1 < nsteps) issue(r0 + (st + 1) * R, b ^ 1);
+#pragma unroll
+                for (int k0 = 0; k0 < R; k0 += 4) {
+                    const int kk = k0 + (lane >> 4);
+                    const double wk = ws[b][kk];
+                    const double a1 = wk * (double)xs[b][kk][16 * W + (lane & 15)];
+                    const double a2 = wk * (double)xs[b][kk][16 * (7 - W) + (lane & 15)];
+                    double bv[NA];
+#pragma unroll
+                    for (int s = 0; s < NA; ++s) bv[s] = (double)xs[b][kk][16 * (W + s) + (lane & 15)];
+#pragma unroll
+                    for (int s = 0; s < NA; ++s)
+                        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[s], acc[s], 0, 0, 0);
+#pragma unroll
+                    for (int t = 0; t <= W; ++t)
+                        acc[NA + t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, bv[7 - 2 * W + t],
+                                                                          acc[NA + t], 0, 0, 0);
+                }
+                settle();
+            }
+#pragma unroll
+            for (int s = 0; s < NA; ++s) store_block(W, W + s, acc[s]);
+#pragma unroll
+            for (int t = 0; t <= W; ++t) store_block(7 - W, 7 - W + t, acc[NA + t]);
+        };
+        switch (wave) {
+        case 0: run(std::integral_constant<int, 0>()); break;
+        case 1: run(std::integral_constant<int, 1>()); break;
+        case 2: run(std::integral_constant<int, 2>()); break;
+        default: run(std::integral_constant<int, 3>()); break;
+        }
+    } else {
+        const int qi = (wave >> 1) * 64, qj = (wave & 1) * 64;   // this wave's quadrant
+        dv4 acc[4][4];
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) acc[ta][tb] = dv4{0.0, 0.0, 0.0, 0.0};
+        for (int64_t st = 0; st < nsteps; ++st) {
+            const int b = (int)(st & 1);
+            if (st + 1 < nsteps) issue(r0 + (st + 1) * R, b ^ 1);
+#pragma unroll
+            for (int k0 = 0; k0 < R; k0 += 4) {
+                const int kk = k0 + (lane >> 4);
+                const double wk = ws[b][kk];
+                double a[4], bb[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    a[t] = wk * (double)xs[b][kk][qi + 16 * t + (lane & 15)];
+                    bb[t] = (double)xs[b][kk][kTile + qj + 16 * t + (lane & 15)];
+                }
+#pragma unroll
+                for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < 4; ++tb)
+                        acc[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta], bb[tb], acc[ta][tb], 0, 0, 0);
+            }
+            settle();
+        }
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) store_block(qi / 16 + ta, qj / 16 + tb, acc[ta][tb]);
+    }
+}
+
 // H entries from the partials: each thread sums one tile entry over the
 // chunks in chunk order; on a diagonal tile only i <= j is taken and mirrored,
 // so H is exactly symmetric.
@@ -408,7 +550,7 @@ glm_status glm_logpost_grad_hess(glm_ctx* ctx, glm_dataset_id id, const double* 
     const dim3 grid((unsigned)nblk);
     switch (ds.d.dtype) {
     case GLM_F64: hipLaunchKernelGGL(k_hess<GLM_F64>, grid, dim3(kHT), 0, s, p); break;
-    case GLM_F32: hipLaunchKernelGGL(k_hess<GLM_F32>, grid, dim3(kHT), 0, s, p); break;
+    case GLM_F32: hipLaunchKernelGGL(k_hess_lds, grid, dim3(kHT), 0, s, p); break;
     case GLM_BF16: hipLaunchKernelGGL(k_hess<GLM_BF16>, grid, dim3(kHT), 0, s, p); break;
     default: hipLaunchKernelGGL(k_hess<GLM_FP8_E4M3>, grid, dim3(kHT), 0, s, p); break;
     }

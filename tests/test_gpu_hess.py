@@ -82,6 +82,25 @@ def test_f32_shapes(ctx, K, N):
     assert out[0] == f and np.array_equal(out[1:], gg)
 
 
+@pytest.mark.parametrize("K", [5, 130, 260])
+def test_f32_nan_row_padding(ctx, K):
+    """FP32 rows whose padding past column K (up to a leading dimension 12
+    columns wider) holds NaN: the padding may reach the staged tile, but only
+    entries past K could see it, and those are not in H."""
+    g = np.random.default_rng(K + 5)
+    N = 20_011
+    X = g.standard_normal((N, K)).astype(np.float32)
+    beta = g.standard_normal(K) / math.sqrt(K)
+    y = (g.random(N) < 0.5).astype(np.uint8)
+    ld = (K + 3) // 4 * 4 + 12
+    buf = torch.full((N, ld), float("nan"), dtype=torch.float32, device=DEV)
+    buf[:, :K] = to_dev(X)
+    Xd, yd = buf[:, :K], to_dev(y)
+    out, H = _hess_gpu(ctx, Xd, yd, beta, 0.7)
+    assert np.isfinite(H).all() and np.isfinite(out).all()
+    _check(H, oracle.hessian(X, beta, 0.7), _bound(X.astype(np.float64), beta))
+
+
 @pytest.mark.parametrize("kind", ["f64", "bf16", "fp8", "poisson"])
 def test_other_storage_and_poisson(ctx, kind):
     g = np.random.default_rng(7)
