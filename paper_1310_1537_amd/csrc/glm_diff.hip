@@ -248,42 +248,40 @@ __global__ __launch_bounds__(NT) void k_diff_eval(DiffParams p) {
     __syncthreads();
     if (!s_last) return;
 
-    __shared__ double s_red[NT];
-    double b = 0.0;   // sum over i != k of (beta_i - m_i)^2
-    for (int i = threadIdx.x; i < p.K; i += NT) {
-        if (i == p.k) continue;
-        const double di = p.beta[i] - (p.mean ? p.mean[i] : 0.0);
-        b += di * di;
-    }
-    s_red[threadIdx.x] = b;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s_red[threadIdx.x] += s_red[threadIdx.x + w];
-        __syncthreads();
-    }
     // 16 fixed interleaved subsets of the blocks per step size, then the
     // subsets in order: a fixed summation order with the loads spread over
-    // the block
+    // the block.  The prior's sum over i != k of (beta_i - m_i)^2 is taken
+    // in the same round trip: thread t adds i = t, t + NT, ..., each wave
+    // adds its lanes by butterfly, the waves are added in order.
     __shared__ double s_m[16][DMAX];
+    __shared__ double s_wb[NT / 64];
     {
         const int j = threadIdx.x & 15, g = threadIdx.x >> 4;   // NT >= 256: g covers 0..15
-        if (g < 16) {
-            double v = 0.0;
-            if (j < nd) {
+        double v = 0.0;
+        if (g < 16 && j < nd) {
 #pragma unroll 8
-                for (int blk = g; blk < (int)gridDim.x; blk += 16)
-                    v += glmk::fetch_published(&p.partials[(int64_t)blk * nd + j]);
-            }
-            if (j < DMAX) s_m[g][j] = v;
+            for (int blk = g; blk < (int)gridDim.x; blk += 16)
+                v += glmk::fetch_published(&p.partials[(int64_t)blk * nd + j]);
         }
+        double b = 0.0;
+        for (int i = threadIdx.x; i < p.K; i += NT) {
+            const double di = p.beta[i] - (p.mean ? p.mean[i] : 0.0);
+            b += i == p.k ? 0.0 : di * di;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) b += __shfl_xor(b, off, 64);
+        if (g < 16 && j < DMAX) s_m[g][j] = v;
+        if (lane == 0) s_wb[wave] = b;
     }
     __syncthreads();
     if (threadIdx.x < nd) {
         const int j = threadIdx.x;
         double f = 0.0;
         for (int g = 0; g < 16; ++g) f += s_m[g][j];
+        double b = 0.0;
+        for (int w = 0; w < NT / 64; ++w) b += s_wb[w];
         const double dk = p.beta[p.k] + p.deltas[j] - (p.mean ? p.mean[p.k] : 0.0);
-        p.out[j] = f - 0.5 * p.prec * (s_red[0] + dk * dk);
+        p.out[j] = f - 0.5 * p.prec * (b + dk * dk);
     }
     if (threadIdx.x == 0)
         __hip_atomic_store(p.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
