@@ -1125,6 +1125,10 @@ def bench_diff(args):
                    "commit_us_avg": float(cm_ms.mean() * 1e3),
                    "f_evals_per_s_kernel": nd / float(ev_ms.mean() * 1e-3)}
         print(f"[bench] diff nd={nd}: {res[nd]}", file=sys.stderr, flush=True)
+    # the per-row terms alone on the same grid, no memory traffic: the floor
+    # that the one-step evaluation is bound by (timed back to back)
+    map_floor_us = glm.glm_probe_diff_map(ctx, N, 0, 20)
+    empty_us = glm.glm_probe_diff_map(ctx, 0, 0, 20)
     eval_bytes = float(N) * (4 + 8 + 1)
     commit_bytes = float(N) * (4 + 8 + 8)
     r1 = res[1]
@@ -1144,7 +1148,13 @@ def bench_diff(args):
                      "traffic": measured_traffic("k_diff_eval_diff_update", "diff"),
                      "bytes_per_launch": eval_bytes, "launch_us_avg": r1["eval_us_avg"],
                      "note": "column k is new each step; u (32 MB) and y (4 MB) are re-read "
-                             "every step and may be served from the 256 MB Infinity Cache"},
+                             "every step and may be served from the 256 MB Infinity Cache",
+                     "map_floor_us": map_floor_us, "empty_launch_us": empty_us,
+                     "frac_of_map_floor": map_floor_us / r1["eval_us_avg"],
+                     "map_note": "the FP64 per-row terms of N rows alone on the evaluation's "
+                                 "grid with no loads (glm_probe_diff_map), back to back, "
+                                 "launch included (empty_launch_us for zero rows): the "
+                                 "evaluation is bound by them, not by its bytes"},
         "by_candidates": {str(k): v for k, v in res.items()},
         "commit_GBps": commit_bytes / (res[1]["commit_us_avg"] * 1e-6) / 1e9,
         "linpred_ms": linpred_ms,

@@ -587,6 +587,17 @@ glm_status glm_probe_read_bandwidth(glm_ctx* ctx, const void* buf, int64_t bytes
  * (NULL, iters < 1), GLM_ENOMEM, GLM_EHIP. */
 glm_status glm_probe_mfma_f64(glm_ctx* ctx, int32_t iters, double* tflops);
 
+/* The measured floor that the differential-update evaluation (Sec. 3.4.4) is
+ * compared with: its per-row term t(u) = y u - b(u) for the response family
+ * (GLM_LOGISTIC or GLM_POISSON) over n synthetic rows (u spread over
+ * [-2, 2.1) by the row index, y from the row index), on the evaluation's
+ * grid and block size, with no memory traffic.  One untimed launch, then
+ * `iters` launches back to back timed with events on the context's stream;
+ * writes the mean microseconds per launch to *us.  Blocks until done.
+ * Errors: GLM_EINVAL (NULL, n < 0, iters < 1, unknown family), GLM_ENOMEM,
+ * GLM_EHIP. */
+glm_status glm_probe_diff_map(glm_ctx* ctx, int64_t n, int32_t family, int32_t iters, double* us);
+
 /* ----------------------------------------------------- storage conversions */
 
 /* BF16 copy of an FP32 matrix, round to nearest even (NaN stays NaN).

@@ -310,6 +310,25 @@ __global__ __launch_bounds__(kThreads) void k_diff_commit(const void* __restrict
 constexpr int kEvalThreadsSmall = 1024;
 constexpr int kEvalThreadsLarge = 512;
 
+// The evaluation's grid: one block per compute unit at most, each block
+// covering at least four rows per lane of a 512-lane block.
+int eval_grid(const glm_ctx* ctx, int64_t N) {
+    return (int)std::max<int64_t>(
+        1, std::min<int64_t>(ctx->num_cu, (N + kEvalThreadsLarge * 4 - 1) / (kEvalThreadsLarge * 4)));
+}
+
+// The per-row terms alone (glm_probe_diff_map): row n's u and y come from n,
+// nothing is loaded; each lane's sum goes to sink so that the work is kept.
+__global__ __launch_bounds__(kEvalThreadsSmall) void k_map_probe(double* __restrict__ sink,
+                                                                 int64_t N, int fam) {
+    const int64_t gtid = (int64_t)blockIdx.x * kEvalThreadsSmall + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kEvalThreadsSmall;
+    double acc = 0.0;
+    for (int64_t n = gtid; n < N; n += stride)
+        acc += row_term((double)(n & 4095) * 1e-3 - 2.0, (unsigned)n, fam);
+    sink[gtid] = acc;
+}
+
 template <int DT>
 const void* diff_kernel_dt(int nd) {
     if (nd <= 1) return reinterpret_cast<const void*>(&k_diff_eval<DT, 1, kEvalThreadsSmall>);
@@ -475,8 +494,7 @@ glm_status glm_diff_logpost(glm_ctx* ctx, glm_dataset_id id, const double* u, co
     if (d.N > 0 && !u) GLM_FAIL(GLM_EINVAL, "glm_diff_logpost: u is NULL");
     st = use_device(ctx);
     if (st != GLM_OK) return st;
-    const int grid = (int)std::max<int64_t>(
-        1, std::min<int64_t>(ctx->num_cu, (d.N + kEvalThreadsLarge * 4 - 1) / (kEvalThreadsLarge * 4)));
+    const int grid = eval_grid(ctx, d.N);
     Scratch* sc = nullptr;
     st = get_scratch(ctx, stream, (size_t)grid * kDMax, 0, 1, &sc);
     if (st != GLM_OK) return st;
@@ -536,6 +554,43 @@ glm_status glm_diff_commit(glm_ctx* ctx, glm_dataset_id id, double* u, double* b
     default: hipLaunchKernelGGL(k_diff_commit<GLM_FP8_E4M3>, dim3(grid), dim3(kThreads), 0, s, col, sk, d.N, delta, u, beta, k); break;
     }
     GLM_HIP_CHECK(hipGetLastError());
+    return GLM_OK;
+}
+
+glm_status glm_probe_diff_map(glm_ctx* ctx, int64_t n, int32_t family, int32_t iters, double* us) {
+    clear_error();
+    if (!ctx || !us || n < 0 || iters < 1) GLM_FAIL(GLM_EINVAL, "glm_probe_diff_map: bad argument");
+    if (family != GLM_LOGISTIC && family != GLM_POISSON)
+        GLM_FAIL(GLM_EINVAL, "glm_probe_diff_map: unknown family %d", family);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    glm_status st = use_device(ctx);
+    if (st != GLM_OK) return st;
+    const int grid = eval_grid(ctx, n);
+    double* sink = nullptr;
+    if (hipMalloc((void**)&sink, (size_t)grid * kEvalThreadsSmall * sizeof(double)) != hipSuccess)
+        GLM_FAIL(GLM_ENOMEM, "glm_probe_diff_map: device allocation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    hipStream_t s = ctx->own_stream;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_map_probe, dim3(grid), dim3(kEvalThreadsSmall), 0, s, sink, n, family);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int i = 0; i < iters && e == hipSuccess; ++i) {
+        hipLaunchKernelGGL(k_map_probe, dim3(grid), dim3(kEvalThreadsSmall), 0, s, sink, n, family);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    if (e != hipSuccess) GLM_FAIL(GLM_EHIP, "glm_probe_diff_map: %s", hipGetErrorString(e));
+    *us = (double)ms * 1e3 / iters;
     return GLM_OK;
 }
 

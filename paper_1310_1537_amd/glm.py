@@ -131,6 +131,7 @@ _SIGS = {
     "glm_probe_roundtrip": [_P, _I32, _I32, ctypes.POINTER(_D)],
     "glm_probe_read_bandwidth": [_P, _P, _I64, _I32, _I32, ctypes.POINTER(_D)],
     "glm_probe_mfma_f64": [_P, _I32, ctypes.POINTER(_D)],
+    "glm_probe_diff_map": [_P, _I64, _I32, _I32, ctypes.POINTER(_D)],
     "glm_quantize_bf16": [_P, _P, _I64, _I32, _I64, _P, _I64, _P],
     "glm_fp8_col_scales": [_P, _P, _I64, _I32, _I64, _P, _P],
     "glm_quantize_fp8": [_P, _P, _I64, _I32, _I64, _P, _P, _I64, _P],
@@ -521,6 +522,14 @@ def glm_probe_mfma_f64(ctx: int, iters: int = 2000) -> float:
     tf = ctypes.c_double()
     _check(_lib.glm_probe_mfma_f64(ctx, iters, ctypes.byref(tf)))
     return tf.value
+
+
+def glm_probe_diff_map(ctx: int, n: int, family: int = 0, iters: int = 20) -> float:
+    """Microseconds per launch of the differential update's per-row terms
+    alone over n synthetic rows (no memory traffic)."""
+    us = ctypes.c_double()
+    _check(_lib.glm_probe_diff_map(ctx, n, family, iters, ctypes.byref(us)))
+    return us.value
 
 
 def glm_quantize_bf16(ctx: int, X, Q, stream=None) -> None:

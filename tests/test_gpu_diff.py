@@ -195,3 +195,14 @@ def test_empty_data_and_errors(ctx):
     with pytest.raises(glm.GlmError) as e:
         glm.glm_linpred(ctx, cs, bd, out)
     assert e.value.status == glm.GLM_ENOTFOUND
+
+
+def test_probe_diff_map(ctx):
+    """The per-row map probe runs for both families and rejects bad arguments."""
+    for fam in (glm.GLM_LOGISTIC, glm.GLM_POISSON):
+        us = glm.glm_probe_diff_map(ctx, 1_000_000, fam, 3)
+        assert 0.0 < us < 1e5
+    assert glm.glm_probe_diff_map(ctx, 0, 0, 2) > 0.0
+    for bad in ((-1, 0, 2), (100, 7, 2), (100, 0, 0)):
+        with pytest.raises(glm.GlmError):
+            glm.glm_probe_diff_map(ctx, *bad)
