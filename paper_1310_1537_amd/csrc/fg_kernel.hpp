@@ -901,11 +901,13 @@ struct WaveTile {
                             for (int e = 0; e < VE; ++e) sacc = fma(xd[j][i][e], bd[b][i][e], sacc);
                             continue;
                         }
-                        u32x4 raw = t.x[j][i];
                         // with several vectors, convert again per vector rather
                         // than keep the converted tile alive (2 registers per
-                        // value): the empty asm hides that raw is unchanged
-                        if constexpr (NB > 1) asm volatile("" : "+v"(raw));
+                        // value): the empty asm hides that the tile is
+                        // unchanged, in place (on a copy, the copy cost two
+                        // moves per chunk and vector)
+                        if constexpr (NB > 1) asm volatile("" : "+v"(t.x[j][i]));
+                        const u32x4 raw = t.x[j][i];
                         float xv[VE];
                         decode_chunk<DT>(raw, xv);
 #pragma unroll
