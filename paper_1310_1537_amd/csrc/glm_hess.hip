@@ -17,7 +17,9 @@
 //      ranges (and w) into LDS and its four waves accumulate 16 x 16 MFMA
 //      blocks, four rows per instruction: on an off-diagonal tile a 64 x 64
 //      quadrant (4 x 4 blocks) each, on a diagonal tile 9 of the 36 blocks on
-//      or above the diagonal each; the block writes its partial tile;
+//      or above the diagonal each; the block writes its partial tile (FP32
+//      rows take k_hess_lds, the same work with the rows loaded straight
+//      into LDS);
 //   3. k_hess_merge: one thread per tile entry adds the tile's partials in
 //      chunk order and writes the entry and its mirror image, minus prec on
 //      the diagonal.
