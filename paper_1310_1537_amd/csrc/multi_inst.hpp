@@ -19,21 +19,29 @@ constexpr int WPB = 4;
 // spilled to scratch and ran 144 us per vector over 2 GB against 125 with 4
 // vectors.)
 //
-// Two geometries take 4 row slots instead, where the tile then fits in FP64
-// once for all vectors (times over 2 GB):
+// These geometries take 4 row slots instead (times over 2 GB):
 //  - FP32 rows of 512 columns (64 lanes x 2 chunks) with 2 vectors, with a
-//    ring of 3 tiles: 309 us against 331 with 8 slots (with 4 vectors 8 slots
-//    stay faster, 447 against 480 us);
-//  - BF16 rows of at most 32 columns (one chunk on at most 4 lanes): a pass
-//    of 4 vectors 2491 against 2877 us at 8 columns, 1158 against 1333 at 32.
-//    (At 128 and 512 columns 8 slots stay faster: 508 against 556 us and 486
-//    against 553 for 2 vectors.)
+//    ring of 3 tiles (the tile then fits in FP64 once for all vectors): 309
+//    us against 331 with 8 slots (with 4 vectors 8 slots stay faster, 447
+//    against 480 us);
+//  - FP32 rows of 1024 columns (4 chunks per lane), with a ring of 3 tiles:
+//    333 us against 561 for 2 vectors (8 slots spilled to scratch memory);
+//  - FP64 rows of 2 or 4 chunks per lane (256 or 512 columns): 345 against
+//    810 us for 4 vectors at 512 columns (8 slots spilled), 315 against 333
+//    for 2; 525 against 607 for 8 vectors at 256 columns, 320 against 377
+//    for 4;
+//  - BF16 rows of at most 32 columns (one chunk on at most 4 lanes; the tile
+//    then fits in FP64 once): a pass of 4 vectors 2491 against 2877 us at 8
+//    columns, 1158 against 1333 at 32.  (At 128 and 512 columns 8 slots stay
+//    faster: 508 against 556 us and 486 against 553 for 2 vectors.)
 template <int DT, int LPR, int CPL, int NB>
 MultiInst minst() {
     constexpr int VE = 16 / glmk::ElemSize<DT>::v;
-    constexpr bool F32_WIDE = DT == glmk::DT_F32 && LPR == 64 && CPL == 2 && NB == 2;
+    constexpr bool F32_WIDE =
+        DT == glmk::DT_F32 && LPR == 64 && ((CPL == 2 && NB == 2) || CPL == 4);
+    constexpr bool F64_WIDE = DT == glmk::DT_F64 && LPR == 64 && CPL >= 2;
     constexpr bool BF16_NARROW = DT == glmk::DT_BF16 && CPL == 1 && LPR <= 4;
-    constexpr int R = F32_WIDE || BF16_NARROW ? 4 : 8;
+    constexpr int R = F32_WIDE || F64_WIDE || BF16_NARROW ? 4 : 8;
     constexpr int NBUF = F32_WIDE ? 3 : 2;
     if constexpr (NB * CPL * VE > 32) {
         return MultiInst{};

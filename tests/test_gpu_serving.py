@@ -94,6 +94,25 @@ def test_multi_bf16_short_rows(ctx, K, nb):
     glm.glm_dataset_unregister(ctx, ds)
 
 
+@pytest.mark.parametrize("K,dt", [(200, np.float64), (256, np.float64), (300, np.float64),
+                                  (512, np.float64), (600, np.float32), (1024, np.float32)])
+@pytest.mark.parametrize("nb", [2, 3, 4, 8])
+def test_multi_wide_rows(ctx, K, dt, nb):
+    """Rows of 2 to 4 chunks per lane (FP64 rows of 129 to 512 columns, FP32
+    rows of 513 to 1024), the instances with 4 row slots, against the oracle
+    at beta and at beta = 0."""
+    X, y, bt = _data(9_001, K, 5 * K + nb, dt)
+    B = _betas(bt, nb, 11)
+    Xd, yd = to_dev(X), to_dev(y)
+    ds = glm.glm_dataset_register(ctx, glm.make_desc(Xd, yd))
+    storage = "f64" if dt == np.float64 else "f32"
+    for Bc in (B, np.zeros_like(B)):
+        o = _multi(ctx, ds, Bc, K)
+        for b in range(nb):
+            _check(o[b, 0], o[b, 1:], X.astype(np.float64), y, Bc[b], 0.01, storage=storage)
+    glm.glm_dataset_unregister(ctx, ds)
+
+
 def test_multi_result_independent_of_companions(ctx):
     """Slot 0 of a pass gives the same bits whatever the other slots hold."""
     X, y, bt = _data(30_000, 128, 4)
