@@ -47,10 +47,11 @@ constexpr int WPB = 4;
 
 // Row slots per lane: 16 slots of 16 bytes, or 8 for FP32 (its FP64
 // gradient products keep r in FP64; 8 slots keep two waves per SIMD),
-// divided by the chunks per lane of wide rows.
+// divided by the chunks per lane of wide rows; FP8 rows of 4 chunks per
+// lane take one slot, as in the plain kernel (4 spilled to scratch memory).
 template <int DT, int CPL>
 constexpr int rb() {
-    return (DT == glmk::DT_F32 ? 8 : 16) / CPL;
+    return DT == glmk::DT_FP8 && CPL == 4 ? 1 : (DT == glmk::DT_F32 ? 8 : 16) / CPL;
 }
 
 struct BInst {

@@ -30,7 +30,10 @@ Inst inst() {
     // and FP32 and FP64 gain nothing from a third tile.
     constexpr bool WIDE = DT == glmk::DT_FP8 && CPL == 1 && LPR >= 32;
     constexpr int RE = DT == glmk::DT_F32 ? 8 : 16;
-    constexpr int R = RE / CPL > 0 ? RE / CPL : 1;
+    // FP8 rows of 4 chunks per lane (4096 columns) take one row slot: with
+    // the 4 of RE / CPL they spilled to scratch memory (2 GB of codes: 707
+    // against 912 us; 2 slots 738).
+    constexpr int R = DT == glmk::DT_FP8 && CPL == 4 ? 1 : (RE / CPL > 0 ? RE / CPL : 1);
     constexpr int NBUF = WIDE ? 3 : 2;
     return Inst{reinterpret_cast<const void*>(&glmk::fg_fused<DT, LPR, CPL, R, WPB, 1, NBUF>), R};
 }
