@@ -34,6 +34,9 @@ constexpr int WPB = 4;
 //    then fits in FP64 once): a pass of 4 vectors 2491 against 2877 us at 8
 //    columns, 1158 against 1333 at 32.  (At 128 and 512 columns 8 slots stay
 //    faster: 508 against 556 us and 486 against 553 for 2 vectors.)
+// Elsewhere 8 slots measured faster, e.g. 8 vectors over FP64 rows of 128
+// columns 570 against 749 us, over FP32 rows of 256 columns 747 against
+// 1027; 2 vectors over BF16 rows of 1024 columns 489 against 551.
 template <int DT, int LPR, int CPL, int NB>
 MultiInst minst() {
     constexpr int VE = 16 / glmk::ElemSize<DT>::v;
