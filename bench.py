@@ -1363,8 +1363,9 @@ def bench_hessian(args):
 
 def bench_multi(args):
     """Several coefficient vectors per pass (glm_logpost_grad_multi) over about
-    2 GB of X for every storage type and row width of the serving workload:
-    microseconds per launch and per vector at 1, 2, 4 and 8 vectors; for BF16
+    2 GB of X for every storage type and row width of the serving workload,
+    and for FP64 rows of the same widths: microseconds per launch and per
+    vector at 1, 2, 4 and 8 vectors; for BF16
     rows of 65 columns and more at 4 and 8 vectors, the matrix-core form beside
     the VALU one (context option GLM_OPT_MATRIX_CORES = 0).  X ~ N(0, 1) drawn on the device (BF16 codes
     by the library's encoder), y ~ Bernoulli(1/2), beta ~ N(0, 0.01^2 I).
@@ -1402,12 +1403,13 @@ def bench_multi(args):
     t0 = time.perf_counter()
     try:
         for K in (8, 32, 128, 512):
-            for dt in ("f32", "bf16"):
-                es = 4 if dt == "f32" else 2
+            for dt in ("f32", "bf16", "f64"):
+                es = {"f32": 4, "bf16": 2, "f64": 8}[dt]
                 N = int(2.0e9 // (K * es))
-                X = torch.randn((N, K), device=dev, dtype=torch.float32, generator=gen)
+                X = torch.randn((N, K), device=dev,
+                                dtype=torch.float64 if dt == "f64" else torch.float32, generator=gen)
                 y = (torch.rand(N, device=dev, generator=gen) < 0.5).to(torch.uint8)
-                code = glm.GLM_F32
+                code = glm.GLM_F64 if dt == "f64" else glm.GLM_F32
                 if dt == "bf16":
                     Q = torch.empty((N, K), dtype=torch.uint16, device=dev)
                     glm.glm_quantize_bf16(ctx, X, Q)
@@ -1444,8 +1446,9 @@ def bench_multi(args):
         "n_gpus": 1, "steps": reps, "warmup": 3, "ms_per_step": keep["us_per_launch"] / 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "several beta per pass: about 2 GB of X per storage type and K in "
-                               "{8, 32, 128, 512}; headline BF16 K=512, 4 vectors, matrix cores",
+        "config": {"workload": "several beta per pass: about 2 GB of X per storage type (FP32, "
+                               "BF16, FP64) and K in {8, 32, 128, 512}; headline BF16 K=512, "
+                               "4 vectors, matrix cores",
                    "N": keep["N"], "K": 512},
         "roofline": {"bound": "hbm", "achieved": keep["GBps_x_once"], "peak": 8000.0, "unit": "GB/s",
                      "frac": keep["GBps_x_once"] / 8000.0,
