@@ -148,7 +148,7 @@ glm_status glm_destroy(glm_ctx* ctx);
  *   GLM_OPT_INTERLEAVE     1 (default): the waves sweep row batches grid-
  *                          strided; 0: one contiguous range per wave.  Read
  *                          at registration.
- *   GLM_OPT_MATRIX_CORES   1 (default): BF16 passes of 4 or more vectors with
+ *   GLM_OPT_MATRIX_CORES   1 (default): BF16 passes of 3 or more vectors with
  *                          rows of at most 512 columns run the linear
  *                          predictors on the matrix cores; 0: on the VALU.
  *                          Read when a several-beta kernel is chosen (each
@@ -222,7 +222,7 @@ glm_status glm_logpost_grad_noalloc(glm_ctx* ctx, glm_dataset_id id, const doubl
  * g for each of betas[0..nb-1], with X streamed once per pass of up to 8
  * vectors (the pass width is the largest of 8, 4, 2 that the instance's
  * register budget allows for this K and dtype; larger nb runs several passes).
- * For BF16 storage with 65 <= K <= 512 and nb >= 4 a pass holds 4 vectors and
+ * For BF16 storage with 65 <= K <= 512 and nb >= 3 a pass holds 4 vectors and
  * their linear predictors X beta run on the matrix cores, with each beta
  * split into four BF16 pieces (about 32 significant bits); the result has the
  * accuracy of the other storage forms' FP32 hi/lo split.

@@ -156,7 +156,7 @@ struct MultiInst {
     const void* fleet = nullptr;   // the same geometry over several data sets per launch
     int wpb = 4;                   // waves per block of both forms
 };
-// The several-beta instance for nb_max vectors per pass; BF16 passes of four
+// The several-beta instance for nb_max vectors per pass; BF16 passes of three
 // or more take the matrix-core form when mx is set and one exists.
 MultiInst multi_instance(int dtype, int lpr, int cpl, int nb_max, bool mx);
 
